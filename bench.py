@@ -1,0 +1,172 @@
+"""Throughput of the batched simplex cross-map on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one pass of the whole hot path (ingest, embedding, library draws,
+gather, fused distance / top-(E+1) / prediction / Pearson kernel, rho
+finalize) over the parameter-sweep workload: coupled logistic map, N=10^4,
+E=1..10, tau=1..5, 20 library sizes log-spaced 100..10^4, r=250, both
+directions -- 500 000 rho values and ~5e9 cross-map predictions per step.
+The series are resident in device memory before the timed region starts.
+
+Prints one JSON line: value = cross-map predictions per second, plus
+rho-realizations per second, the roofline of the cross-map kernel (binary32
+flops per pair 3E-1, over the summed HIP-event duration of its launches) and
+the CPU oracle timed on a bounded random sample of the same realizations.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1905_00565_amd import capi, synth  # noqa: E402
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--r", type=int, default=250, help="realizations per L")
+    ap.add_argument("--n", type=int, default=10000, help="series length")
+    ap.add_argument("--flags", type=int, default=0, help="CCM_FLAG_* bits")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall-clock budget of the CPU oracle sample (0: skip)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle on a seeded random sample of the workload's realizations."""
+    import oracle
+    orc = oracle.default()
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(12345)
+    X, Y = w.X, w.Y
+    grid = [(e, t, l) for e in w.E for t in w.tau for l in w.L]
+    done_preds = 0.0
+    done = 0
+    t0 = time.perf_counter()
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(task):
+        e, t, l, ri, d = task
+        S, T = (Y, X) if d == 0 else (X, Y)
+        orc.realization(S, T, e, t, l, ri, w.seed)
+        return w.N - (e - 1) * t        # predictions (every embedded point)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        while time.perf_counter() - t0 < budget_s:
+            batch = []
+            for _ in range(threads):
+                e, t, l = grid[int(rng.integers(len(grid)))]
+                batch.append((e, t, l, int(rng.integers(w.r)), int(rng.integers(2))))
+            for p in ex.map(one, batch):
+                done_preds += p
+                done += 1
+    el = time.perf_counter() - t0
+    return {"value": done_preds / el, "unit": "predictions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{done} realizations drawn uniformly at random (seed 12345) from "
+                      f"the {len(grid) * w.r * 2} of the workload, {el:.1f} s on "
+                      f"{threads} threads"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(the cross map shards by realization, see the design notes)", flush=True)
+        sys.exit(2)
+    import torch
+
+    w = synth.workload_sweep(n=a.n, r=a.r)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.X, device=dev)
+    Y = torch.tensor(w.Y, device=dev)
+    rho = torch.empty((2, len(w.E), len(w.tau), len(w.L), w.r), dtype=torch.float64,
+                      device=dev)
+    stream = torch.cuda.current_stream()
+    ctx = capi.Context(0)
+
+    def step():
+        ctx.ccm_sweep_dev(X, Y, w.E, w.tau, w.L, w.r, w.seed, rho, stream=stream,
+                          flags=a.flags)
+
+    ctx.profile_enable(True)
+    print(f"bench: warmup {a.warmup} step(s) of {w.name}", file=sys.stderr, flush=True)
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_read(reset=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read(reset=True)
+    el = t1 - t0
+    print(f"bench: {a.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
+
+    rh = rho.cpu().numpy()
+    if not np.isfinite(rh).all():
+        print("bench: warning: non-finite rho values", file=sys.stderr, flush=True)
+
+    preds = prof["predictions"]
+    realizations = prof["realizations"]
+    kernel_s = prof["kernel_ms"] / 1e3
+    achieved_tflops = prof["flops"] / kernel_s / 1e12 if kernel_s > 0 else 0.0
+    launches = max(1, prof["launches"])
+    out = {
+        "metric": "cross-map predictions/sec and rho-realizations/sec",
+        "value": preds / el,
+        "unit": "predictions/s",
+        "rho_realizations_per_sec": realizations / el,
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": el / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.N, "E": f"{w.E[0]}..{w.E[-1]}",
+                   "tau": f"{w.tau[0]}..{w.tau[-1]}", "L": w.L, "r": w.r,
+                   "directions": 2, "parallelism": "single GPU",
+                   "realizations_per_step": realizations / a.steps,
+                   "predictions_per_step": preds / a.steps},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_crossmap (fused distance/top-(E+1)/predict/moments)",
+            "achieved": achieved_tflops,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "launches_per_step": launches / a.steps,
+            "avg_launch_ms": prof["kernel_ms"] / launches,
+            "kernel_share_of_step": kernel_s / el,
+            "pairs_per_step": prof["pairs"] / a.steps,
+        },
+    }
+    if a.cpu_seconds > 0:
+        print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

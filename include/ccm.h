@@ -1,0 +1,199 @@
+/*
+ * ccm.h -- C ABI of libccm: batched simplex cross-map prediction, the hot
+ * path of convergent cross mapping (CCM), on one AMD Instinct MI355X (gfx950).
+ *
+ * What a call computes (paper: Pu, Duan & Osgood, "Parallelizing Convergent
+ * Cross Mapping Using Apache Spark"):
+ *   For series X and Y, embedding dimension E and delay tau (Introduction:
+ *   the parameters r, tau, E, L), build the lagged-coordinate shadow manifold
+ *   of the library series; for each library size L draw r random library
+ *   subsamples (Introduction; Section 3.1: the input record is a pair of
+ *   subsamples of length L plus (tau, E)); for every query point find its E+1
+ *   nearest library vectors by brute force (Section 3.2: distances to all
+ *   lagged-coordinate vectors, sorted, first E+1); predict the other series
+ *   by simplex projection (Section 2.1) with weights exp(-d_i / d_1); and
+ *   report the Pearson correlation of observed and predicted values as the
+ *   prediction skill (Section 2.1), in both directions (Introduction).  The
+ *   output is one skill per realization: the "sequence of prediction skills"
+ *   of Section 3.1.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - embedded point i (0-based) is at time t_i = i + (E-1) tau, coordinate
+ *     k = S[t_i - k tau]; the predicted value is the target at t_i;
+ *     N_e = N - (E-1) tau embedded points;
+ *   - squared distances are binary32: both series are rounded to float, then
+ *     acc = fma(d_k, d_k, acc), k = 0..E-1 from +0, d_k = q_k - p_k in float;
+ *     neighbours are the first E+1 candidates in (d2, index) order, so ties
+ *     go to the lower time index;
+ *   - d_m = sqrt(d2_m) in double; w_m proportional to exp(-d_m / d_1); when
+ *     d_1 = 0 the weight is shared equally by the zero-distance neighbours;
+ *   - libraries are drawn without replacement by selection sampling driven
+ *     by SplitMix64; the draw of realization r_index depends only on
+ *     (seed, E, tau, L_eff, r_index), so both directions (and every series
+ *     of ccm_matrix) share it;
+ *   - L above N_e is clamped to L_eff = N_e (then every realization is the
+ *     same full library);
+ *   - rho is NaN when the observed or the predicted values are constant.
+ *
+ * Ownership: every pointer argument is borrowed for the duration of the call
+ * (host pointers) or until the work queued on the given stream has run
+ * (device pointers).  Outputs are caller-allocated.  The context owns all
+ * device memory it allocates.
+ *
+ * Threading: a context serialises its calls internally; use one context per
+ * host thread for concurrency.
+ *
+ * Errors: every function returns a ccm_status.  CCM_E_INVAL for a null
+ * pointer, N < 2, E outside [1, 10], tau < 1, N_e < E + 2, any L < E + 2,
+ * an L_eff too small for the exclusion window (L_eff < E + 2 + 2w), r < 1,
+ * nL < 1, a non-finite input value or |value| > 1e17 (which keeps every
+ * binary32 squared distance finite).  CCM_E_NOMEM when device memory cannot
+ * be allocated, CCM_E_DEVICE for any failing HIP call; ccm_last_error()
+ * returns the message.  No C++ exception crosses this interface.
+ */
+#ifndef CCM_H
+#define CCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CCM_OK = 0,
+  CCM_E_INVAL = -1,
+  CCM_E_NOMEM = -2,
+  CCM_E_DEVICE = -3,
+  CCM_E_BUSY = -4,
+  CCM_E_NOTFOUND = -5,
+  CCM_E_TIMEOUT = -6
+} ccm_status;
+
+typedef struct ccm_ctx ccm_ctx;
+
+/* Options (NULL means all defaults). */
+typedef struct {
+  /* 0: drop the query point itself from its candidates (default);
+     -1: keep it; w > 0: drop every candidate j with |j - i| <= w. */
+  int32_t exclusion_radius;
+  /* 0: predict at every embedded point (default); 1: at the library points. */
+  int32_t query_set;
+  /* CCM_FLAG_* bits. */
+  uint32_t flags;
+} ccm_opts;
+
+/* One kernel launch per realization instead of one batched launch (the
+   unbatched baseline the batched form is compared against). */
+#define CCM_FLAG_PLAIN 1u
+/* Issue the batched launches directly instead of replaying a captured
+   HIP graph. */
+#define CCM_FLAG_NO_GRAPH 2u
+/* Cross-map kernel as a persistent grid pulling work items from an atomic
+   queue (default: one workgroup per work item, longest first). */
+#define CCM_FLAG_PERSISTENT 4u
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+ccm_status ccm_create(int device, ccm_ctx **out);
+/* Release the context and all device memory it owns (NULL is a no-op). */
+void ccm_destroy(ccm_ctx *ctx);
+/* Message of the last failing call on this context ("" if none).  The
+   string stays valid until the next call on the context. */
+const char *ccm_last_error(const ccm_ctx *ctx);
+
+/*
+ * Cross map in both directions for one (E, tau): Introduction and
+ * Sections 2.1, 3.1, 3.2.
+ *   X, Y        host double[N] series
+ *   L           host int64[nL] library sizes
+ *   r           realizations (random libraries) per L
+ *   seed        sampler seed
+ *   rho_X_from_MY  host double[nL][r]: skill of predicting X from the
+ *                  manifold of Y (high when X drives Y)
+ *   rho_Y_from_MX  host double[nL][r]
+ *   L_eff       host int64[nL] (nullable): clamped library sizes
+ */
+ccm_status ccm(ccm_ctx *ctx, const double *X, const double *Y, int64_t N,
+               int32_t E, int32_t tau, const int64_t *L, int32_t nL, int32_t r,
+               uint64_t seed, const ccm_opts *opts, double *rho_X_from_MY,
+               double *rho_Y_from_MX, int64_t *L_eff);
+
+/*
+ * Parameter sweep (Introduction: results are sensitive to E, tau and L and
+ * are explored over a range of settings; Section 3.3 runs the settings
+ * concurrently).  All realizations of every (E, tau, L, r) run as one
+ * batched launch per E.
+ *   E, tau      host int32[nE], int32[ntau]
+ *   rho         host double[2][nE][ntau][nL][r]; [0] = X from M_Y,
+ *               [1] = Y from M_X
+ */
+ccm_status ccm_sweep(ccm_ctx *ctx, const double *X, const double *Y,
+                     int64_t N, const int32_t *E, int32_t nE,
+                     const int32_t *tau, int32_t ntau, const int64_t *L,
+                     int32_t nL, int32_t r, uint64_t seed,
+                     const ccm_opts *opts, double *rho);
+
+/*
+ * Device-pointer forms: X, Y (double[N]) and rho are device pointers, the
+ * other arrays are host pointers; the work is queued on `stream` (a
+ * hipStream_t; NULL = the null stream) and the call returns without waiting.
+ * Output layouts as above.
+ */
+ccm_status ccm_dev(ccm_ctx *ctx, const double *X, const double *Y, int64_t N,
+                   int32_t E, int32_t tau, const int64_t *L, int32_t nL,
+                   int32_t r, uint64_t seed, const ccm_opts *opts,
+                   double *rho_X_from_MY, double *rho_Y_from_MX,
+                   int64_t *L_eff, void *stream);
+ccm_status ccm_sweep_dev(ccm_ctx *ctx, const double *X, const double *Y,
+                         int64_t N, const int32_t *E, int32_t nE,
+                         const int32_t *tau, int32_t ntau, const int64_t *L,
+                         int32_t nL, int32_t r, uint64_t seed,
+                         const ccm_opts *opts, double *rho, void *stream);
+
+/*
+ * Test hook: the library subsample the sampler draws for realization
+ * r_index of (E, tau, L_eff) under seed, over N_e embedded points.
+ *   idx_out     host int32[L_eff], ascending embedded-point indices
+ */
+ccm_status ccm_library(ccm_ctx *ctx, int64_t N_e, int32_t E, int32_t tau,
+                       int64_t L_eff, int32_t r_index, uint64_t seed,
+                       int32_t *idx_out);
+
+/*
+ * Test hook: one realization over a caller-given library (Section 3.2 and
+ * 2.1), with every per-query result exported.
+ *   lib_series  host double[N]: series whose manifold is searched
+ *   target      host double[N]: series that is predicted
+ *   lib_idx     host int32[L_eff]: strictly ascending embedded indices
+ *   nbr         host int32[Nq][E+1] (nullable): neighbour indices, nearest
+ *               first; Nq = N_e, or L_eff with query_set = 1
+ *   d2          host float[Nq][E+1] (nullable): their squared distances
+ *   pred        host double[Nq] (nullable): predictions
+ *   rho         host double (nullable): the skill
+ */
+ccm_status ccm_neighbors(ccm_ctx *ctx, const double *lib_series,
+                         const double *target, int64_t N, int32_t E,
+                         int32_t tau, const int32_t *lib_idx, int64_t L_eff,
+                         const ccm_opts *opts, int32_t *nbr, float *d2,
+                         double *pred, double *rho);
+
+/* Kernel timing of the cross-map kernels (HIP events on the launch stream).
+   While enabled, batched calls issue their launches directly (no graph). */
+typedef struct {
+  double kernel_ms;      /* summed duration of cross-map kernel launches */
+  int64_t launches;      /* cross-map kernel launches timed */
+  double pairs;          /* (query, candidate) distance evaluations */
+  double flops;          /* 3E-1 binary32 flops per pair, summed */
+  double predictions;    /* cross-map predictions made */
+  double realizations;   /* rho values produced */
+} ccm_profile;
+
+ccm_status ccm_profile_enable(ccm_ctx *ctx, int on);
+/* Wait for the timed launches, fill *out, and zero the counters if reset. */
+ccm_status ccm_profile_read(ccm_ctx *ctx, ccm_profile *out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCM_H */

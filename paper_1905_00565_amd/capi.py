@@ -1,0 +1,290 @@
+"""ctypes binding of libccm (include/ccm.h), function for function.
+
+Argument marshalling only: every step of the cross map runs in the HIP
+library.  There is no CPU path: if ``libccm.so`` is missing the import of a
+function raises, and if no GPU is present ``ccm_create`` fails.
+
+Host-array functions take numpy arrays; device-pointer functions
+(``ccm_dev``, ``ccm_sweep_dev``) take torch CUDA tensors (or raw integer
+addresses) plus an optional stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(_HERE, "libccm.so")
+
+CCM_OK = 0
+CCM_E_INVAL = -1
+CCM_E_NOMEM = -2
+CCM_E_DEVICE = -3
+CCM_E_BUSY = -4
+CCM_E_NOTFOUND = -5
+CCM_E_TIMEOUT = -6
+
+CCM_FLAG_PLAIN = 1
+CCM_FLAG_NO_GRAPH = 2
+CCM_FLAG_PERSISTENT = 4
+
+# Every symbol include/ccm.h declares (checked by the ABI test).
+EXPORTS = [
+    "ccm_create", "ccm_destroy", "ccm_last_error", "ccm", "ccm_sweep",
+    "ccm_dev", "ccm_sweep_dev", "ccm_library", "ccm_neighbors",
+    "ccm_profile_enable", "ccm_profile_read",
+]
+
+
+class ccm_opts(C.Structure):
+    _fields_ = [("exclusion_radius", C.c_int32), ("query_set", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class ccm_profile(C.Structure):
+    _fields_ = [("kernel_ms", C.c_double), ("launches", C.c_int64),
+                ("pairs", C.c_double), ("flops", C.c_double),
+                ("predictions", C.c_double), ("realizations", C.c_double)]
+
+
+class CCMError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"ccm status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libccm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBRARY):
+            raise RuntimeError(f"{LIBRARY} is missing: build it with "
+                               "`python -m paper_1905_00565_amd.build`")
+        try:
+            # One HIP runtime per process: torch bundles its own copy (same
+            # SONAME); loading it first makes libccm bind to that copy.
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIBRARY)
+        P, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        L.ccm_create.argtypes = [C.c_int, C.POINTER(P)]
+        L.ccm_destroy.argtypes = [P]
+        L.ccm_destroy.restype = None
+        L.ccm_last_error.argtypes = [P]
+        L.ccm_last_error.restype = C.c_char_p
+        L.ccm.argtypes = [P, P, P, i64, i32, i32, P, i32, i32, u64, P, P, P, P]
+        L.ccm_sweep.argtypes = [P, P, P, i64, P, i32, P, i32, P, i32, i32, u64, P, P]
+        L.ccm_dev.argtypes = [P, P, P, i64, i32, i32, P, i32, i32, u64, P, P, P, P, P]
+        L.ccm_sweep_dev.argtypes = [P, P, P, i64, P, i32, P, i32, P, i32, i32, u64, P, P, P]
+        L.ccm_library.argtypes = [P, i64, i32, i32, i64, i32, u64, P]
+        L.ccm_neighbors.argtypes = [P, P, P, i64, i32, i32, P, i64, P, P, P, P, P]
+        L.ccm_profile_enable.argtypes = [P, C.c_int]
+        L.ccm_profile_read.argtypes = [P, C.POINTER(ccm_profile), C.c_int]
+        for name in EXPORTS:
+            if name not in ("ccm_destroy", "ccm_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return C.c_void_p(t)
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _opts(exclusion_radius=0, query_set=0, flags=0):
+    return ccm_opts(int(exclusion_radius), int(query_set), int(flags))
+
+
+def _check(ctx, st):
+    if st != CCM_OK:
+        msg = lib().ccm_last_error(ctx).decode() if ctx else ""
+        raise CCMError(st, msg)
+
+
+# ---------------------------------------------------------------------------
+# functions mirroring the C ABI
+# ---------------------------------------------------------------------------
+
+def ccm_create(device: int = 0) -> C.c_void_p:
+    h = C.c_void_p()
+    st = lib().ccm_create(device, C.byref(h))
+    if st != CCM_OK:
+        raise CCMError(st, f"ccm_create(device={device}) failed")
+    return h
+
+
+def ccm_destroy(ctx) -> None:
+    lib().ccm_destroy(ctx)
+
+
+def ccm_last_error(ctx) -> str:
+    return lib().ccm_last_error(ctx).decode()
+
+
+def ccm(ctx, X, Y, E, tau, L, r, seed, exclusion_radius=0, query_set=0, flags=0):
+    """(rho_X_from_MY [nL][r], rho_Y_from_MX [nL][r], L_eff [nL])."""
+    X, Y = _f64(X), _f64(Y)
+    if len(X) != len(Y):
+        raise ValueError("X and Y must have the same length")
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    nL = len(Ls)
+    rxy = np.empty((nL, r))
+    ryx = np.empty((nL, r))
+    le = np.empty(nL, dtype=np.int64)
+    o = _opts(exclusion_radius, query_set, flags)
+    _check(ctx, lib().ccm(ctx, _ptr(X), _ptr(Y), len(X), E, tau, _ptr(Ls), nL, r,
+                          seed & (2**64 - 1), C.byref(o), _ptr(rxy), _ptr(ryx), _ptr(le)))
+    return rxy, ryx, le
+
+
+def ccm_sweep(ctx, X, Y, E, tau, L, r, seed, exclusion_radius=0, query_set=0, flags=0):
+    """rho [2][nE][ntau][nL][r] ([0]: X from M_Y, [1]: Y from M_X)."""
+    X, Y = _f64(X), _f64(Y)
+    if len(X) != len(Y):
+        raise ValueError("X and Y must have the same length")
+    Es = np.ascontiguousarray(E, dtype=np.int32)
+    Ts = np.ascontiguousarray(tau, dtype=np.int32)
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    rho = np.empty((2, len(Es), len(Ts), len(Ls), r))
+    o = _opts(exclusion_radius, query_set, flags)
+    _check(ctx, lib().ccm_sweep(ctx, _ptr(X), _ptr(Y), len(X), _ptr(Es), len(Es), _ptr(Ts),
+                                len(Ts), _ptr(Ls), len(Ls), r, seed & (2**64 - 1),
+                                C.byref(o), _ptr(rho)))
+    return rho
+
+
+def ccm_dev(ctx, X, Y, E, tau, L, r, seed, rho_xy, rho_yx, stream=None,
+            exclusion_radius=0, query_set=0, flags=0, N=None):
+    """Device form: X, Y, rho_xy, rho_yx are torch CUDA tensors (or addresses)."""
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    le = np.empty(len(Ls), dtype=np.int64)
+    n = int(N if N is not None else X.numel())
+    o = _opts(exclusion_radius, query_set, flags)
+    _check(ctx, lib().ccm_dev(ctx, _dev_ptr(X), _dev_ptr(Y), n, E, tau, _ptr(Ls), len(Ls),
+                              r, seed & (2**64 - 1), C.byref(o), _dev_ptr(rho_xy),
+                              _dev_ptr(rho_yx), _ptr(le), _stream_ptr(stream)))
+    return le
+
+
+def ccm_sweep_dev(ctx, X, Y, E, tau, L, r, seed, rho, stream=None,
+                  exclusion_radius=0, query_set=0, flags=0, N=None):
+    """Device form of ccm_sweep: rho is a device double[2][nE][ntau][nL][r]."""
+    Es = np.ascontiguousarray(E, dtype=np.int32)
+    Ts = np.ascontiguousarray(tau, dtype=np.int32)
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    n = int(N if N is not None else X.numel())
+    o = _opts(exclusion_radius, query_set, flags)
+    _check(ctx, lib().ccm_sweep_dev(ctx, _dev_ptr(X), _dev_ptr(Y), n, _ptr(Es), len(Es),
+                                    _ptr(Ts), len(Ts), _ptr(Ls), len(Ls), r,
+                                    seed & (2**64 - 1), C.byref(o), _dev_ptr(rho),
+                                    _stream_ptr(stream)))
+
+
+def ccm_library(ctx, N_e, E, tau, L_eff, r_index, seed):
+    out = np.empty(max(int(L_eff), 1), dtype=np.int32)
+    _check(ctx, lib().ccm_library(ctx, N_e, E, tau, L_eff, r_index, seed & (2**64 - 1),
+                                  _ptr(out)))
+    return out[:L_eff]
+
+
+def ccm_neighbors(ctx, lib_series, target, E, tau, lib_idx, exclusion_radius=0,
+                  query_set=0):
+    """(nbr [Nq][E+1], d2 [Nq][E+1] float32, pred [Nq], rho) of one library."""
+    S, T = _f64(lib_series), _f64(target)
+    li = np.ascontiguousarray(lib_idx, dtype=np.int32)
+    N = len(S)
+    ne = N - (E - 1) * tau
+    nq = len(li) if query_set else ne
+    nbr = np.empty((max(nq, 1), E + 1), dtype=np.int32)
+    d2 = np.empty((max(nq, 1), E + 1), dtype=np.float32)
+    pred = np.empty(max(nq, 1), dtype=np.float64)
+    rho = C.c_double()
+    o = _opts(exclusion_radius, query_set, 0)
+    _check(ctx, lib().ccm_neighbors(ctx, _ptr(S), _ptr(T), N, E, tau, _ptr(li), len(li),
+                                    C.byref(o), _ptr(nbr), _ptr(d2), _ptr(pred),
+                                    C.byref(rho)))
+    return nbr[:nq], d2[:nq], pred[:nq], rho.value
+
+
+def ccm_profile_enable(ctx, on=True):
+    _check(ctx, lib().ccm_profile_enable(ctx, 1 if on else 0))
+
+
+def ccm_profile_read(ctx, reset=True) -> dict:
+    p = ccm_profile()
+    _check(ctx, lib().ccm_profile_read(ctx, C.byref(p), 1 if reset else 0))
+    return {f: getattr(p, f) for f, _ in ccm_profile._fields_}
+
+
+class Context:
+    """Owns one ccm context; methods forward to the functions above."""
+
+    def __init__(self, device: int = 0):
+        self.handle = ccm_create(device)
+
+    def close(self):
+        if self.handle:
+            ccm_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ccm(self, *a, **k):
+        return ccm(self.handle, *a, **k)
+
+    def ccm_sweep(self, *a, **k):
+        return ccm_sweep(self.handle, *a, **k)
+
+    def ccm_dev(self, *a, **k):
+        return ccm_dev(self.handle, *a, **k)
+
+    def ccm_sweep_dev(self, *a, **k):
+        return ccm_sweep_dev(self.handle, *a, **k)
+
+    def ccm_library(self, *a, **k):
+        return ccm_library(self.handle, *a, **k)
+
+    def ccm_neighbors(self, *a, **k):
+        return ccm_neighbors(self.handle, *a, **k)
+
+    def profile_enable(self, on=True):
+        ccm_profile_enable(self.handle, on)
+
+    def profile_read(self, reset=True):
+        return ccm_profile_read(self.handle, reset)

@@ -1,0 +1,111 @@
+// ccm_internal.h -- descriptors shared by the library's host runtime and its
+// gfx950 kernels.  Internal to libccm; the public boundary is include/ccm.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccmk {
+
+constexpr int kMaxE = 10;          // simplex embedding dimension range is 1..10
+constexpr int kBlock = 256;        // threads per workgroup of the cross-map kernel
+
+// Exclusion handling of the cross-map kernel (compile-time variants).
+enum ExclMode : int {
+  kExclSelf = 0,    // drop the query itself (keep E+2 running slots, drop self after)
+  kKeepSelf = 1,    // every library point is a candidate
+  kWindow = 2,      // drop candidates with |j - i| <= w (per-pair mask)
+};
+
+// One ingest copy: double series -> float series (round to nearest even).
+struct IngestJob {
+  int64_t src_off;   // doubles into the FP64 series pool
+  int64_t dst_off;   // floats into the FP32 series pool
+  int64_t n;
+};
+
+// One embedding: AoS float [n_e][E] with emb[i*E + k] = s[i + (E-1)tau - k tau].
+struct EmbedJob {
+  int64_t src_off;   // floats into the FP32 series pool
+  int64_t dst_off;   // floats into the embedding pool
+  int64_t n_e;
+  int32_t E;
+  int32_t tau;
+};
+
+// One library draw (selection sampling keyed by (seed, E, tau, L_eff, r)).
+struct SampleJob {
+  uint64_t seed;
+  int64_t n_e;
+  int64_t l_eff;
+  int64_t out_off;   // int32 indices into the library pool
+  int32_t E;
+  int32_t tau;
+  int32_t r_index;
+  int32_t pad;
+};
+
+// One realization: a library drawn over one embedding, predicting one target.
+struct Realization {
+  int64_t emb_off;   // floats: AoS embedding of the library series
+  int64_t lib_off;   // int32: library indices (ascending)
+  int64_t pts_off;   // floats: library coordinates gathered, AoS [l_eff][E]
+  int64_t tgt_off;   // doubles: FP64 target series (time 0)
+  int32_t E;
+  int32_t tau;
+  int32_t n_e;       // embedded points of the library series
+  int32_t l_eff;     // library size
+  int32_t n_query;   // queries: n_e, or l_eff when only library points are queried
+  int32_t n_tiles;   // query tiles (= work items) of this realization
+  int64_t slot_base; // first partial-moment slot (one per tile)
+  int64_t out_index; // where rho goes in the caller's output
+};
+
+// One library gather: pts[c*E + k] = emb[lib[c]*E + k] for c < l_eff.
+struct GatherJob {
+  int64_t emb_off;
+  int64_t lib_off;
+  int64_t pts_off;
+  int64_t l_eff;
+  int32_t E;
+  int32_t pad;
+};
+
+// A work item: one query tile of one realization.
+struct Item {
+  int32_t rz;
+  int32_t tile;
+};
+
+// Pearson moments of one query tile: count, means, centred sums (Welford).
+struct Moments {
+  double n, mt, mp, m2t, m2p, c;
+};
+
+// Optional per-query dump (test hook): neighbours, squared distances, predictions.
+struct Dump {
+  int32_t* nbr;   // [n_query][E+1]
+  float* d2;      // [n_query][E+1]
+  double* pred;   // [n_query]
+};
+
+// Launchers (defined with the kernels).
+int crossmap_queries_per_lane(int E, bool dump);
+hipError_t launch_ingest(const IngestJob* jobs, int n_jobs, int64_t max_n,
+                         const double* src, float* dst, hipStream_t st);
+hipError_t launch_embed(const EmbedJob* jobs, int n_jobs, int64_t max_n,
+                        const float* s32, float* emb, hipStream_t st);
+hipError_t launch_sample(const SampleJob* jobs, int64_t n_jobs, int32_t* out,
+                         hipStream_t st);
+hipError_t launch_gather(const GatherJob* jobs, int64_t n_jobs, const float* emb,
+                         const int32_t* lib, float* pts, hipStream_t st);
+hipError_t launch_zero_int(int* p, int n, hipStream_t st);
+hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
+                           const Realization* rzs, const Item* items,
+                           int n_items, int* next, const float* emb,
+                           const int32_t* lib, const float* pts,
+                           const double* tgt, Moments* partial, int query_set,
+                           int window, Dump d, hipStream_t st);
+hipError_t launch_finalize(const Realization* rzs, int64_t n_rz,
+                           const Moments* partial, double* out, hipStream_t st);
+
+}  // namespace ccmk

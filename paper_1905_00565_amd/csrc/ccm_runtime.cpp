@@ -1,0 +1,771 @@
+// ccm_runtime.cpp -- host runtime of libccm: validation, planning of the
+// realization / work-item lists, device buffers, HIP graph capture and
+// replay, and the C ABI declared in include/ccm.h.
+//
+// A call is planned once per distinct shape (series length, E and tau grid,
+// L list, r, seed, options).  The plan's descriptors and buffers live on the
+// device inside an Exec; the launches of a plan are captured into a HIP graph
+// and replayed on later calls of the same shape.  Inputs are copied into the
+// Exec's own series buffer (host-to-device, or device-to-device for the
+// device-pointer forms) and results copied out, so the graph never refers to
+// caller memory.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ccm.h"
+#include "ccm_internal.h"
+
+using namespace ccmk;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+struct Fail {
+  ccm_status status;
+  std::string what;
+};
+
+[[noreturn]] void fail(ccm_status st, const std::string& what) { throw Fail{st, what}; }
+
+void hip_check(hipError_t e, const char* expr) {
+  if (e == hipSuccess) return;
+  const ccm_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+                            ? CCM_E_NOMEM
+                            : CCM_E_DEVICE;
+  fail(st, std::string(expr) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr) hip_check((expr), #expr)
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t n) {
+    if (n <= bytes && p) return;
+    release();
+    if (n == 0) n = 256;
+    HIPCHK(hipMalloc(&p, n));
+    bytes = n;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& v) {
+  b.ensure(v.size() * sizeof(T));
+  if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+
+struct Spec {
+  int64_t N = 0;
+  std::vector<int32_t> E, tau;
+  std::vector<int64_t> L;
+  int32_t r = 0;
+  uint64_t seed = 0;
+  int32_t excl = 0;
+  int32_t query_set = 0;
+  uint32_t flags = 0;
+
+  bool operator==(const Spec& o) const {
+    return N == o.N && E == o.E && tau == o.tau && L == o.L && r == o.r &&
+           seed == o.seed && excl == o.excl && query_set == o.query_set &&
+           (flags & ~CCM_FLAG_NO_GRAPH) == (o.flags & ~CCM_FLAG_NO_GRAPH);
+  }
+};
+
+int excl_mode(int32_t excl) {
+  if (excl == 0) return kExclSelf;
+  if (excl < 0) return kKeepSelf;
+  return kWindow;
+}
+
+int64_t min_library(int32_t E, int32_t excl) {
+  const int64_t w = excl < 0 ? 0 : 2 * (int64_t)excl + 1;
+  return (int64_t)E + 1 + w;
+}
+
+struct Plan {
+  Spec spec;
+  int mode = kExclSelf;
+  int window = 0;
+  std::vector<IngestJob> ingest;
+  int64_t n64 = 0, n32 = 0;
+  std::vector<EmbedJob> embed;
+  int64_t n_emb = 0, max_embed = 0;
+  std::vector<SampleJob> sample;
+  int64_t n_lib = 0;
+  std::vector<GatherJob> gather;
+  int64_t n_pts = 0;
+  std::vector<Realization> rz;
+  // realization r owns sample job rz_sample[r] and gather job r
+  std::vector<int64_t> rz_sample;
+  // batched items grouped by E, longest library first within a group
+  std::vector<Item> items;
+  int e_first[kMaxE + 1] = {0};
+  int e_count[kMaxE + 1] = {0};
+  int64_t n_slots = 0;
+  int64_t n_out = 0;
+  std::vector<int64_t> L_eff;   // per (iE, itau, iL)
+  double pairs = 0, flops = 0, preds = 0;
+  size_t device_bytes = 0;
+};
+
+// Validate a sweep and lay out every realization of it.
+Plan make_plan(const Spec& s) {
+  if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
+  if (s.E.empty() || s.tau.empty() || s.L.empty()) fail(CCM_E_INVAL, "empty E, tau or L list");
+  if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
+  if (s.query_set != 0 && s.query_set != 1) fail(CCM_E_INVAL, "query_set must be 0 or 1");
+  if (s.N > (int64_t)INT32_MAX / 2) fail(CCM_E_INVAL, "N too large");
+  for (int32_t e : s.E)
+    if (e < 1 || e > kMaxE) fail(CCM_E_INVAL, "E must be in [1, 10]");
+  for (int32_t t : s.tau)
+    if (t < 1) fail(CCM_E_INVAL, "tau must be >= 1");
+  for (int32_t e : s.E)
+    for (int32_t t : s.tau) {
+      const int64_t ne = s.N - (int64_t)(e - 1) * t;
+      if (ne < e + 2) fail(CCM_E_INVAL, "N_e = N - (E-1) tau must be >= E + 2");
+      for (int64_t l : s.L) {
+        if (l < e + 2) fail(CCM_E_INVAL, "every L must be >= E + 2");
+        if (std::min(l, ne) < min_library(e, s.excl))
+          fail(CCM_E_INVAL, "library too small for the exclusion window");
+      }
+    }
+
+  Plan p;
+  p.spec = s;
+  p.mode = excl_mode(s.excl);
+  p.window = s.excl > 0 ? s.excl : 0;
+  const int nE = (int)s.E.size(), nT = (int)s.tau.size(), nL = (int)s.L.size();
+  const int64_t N = s.N;
+  p.n64 = 2 * N;
+  p.n32 = 2 * N;
+  p.ingest.push_back({0, 0, 2 * N});
+  p.n_out = 2LL * nE * nT * nL * s.r;
+  p.L_eff.assign((size_t)nE * nT * nL, 0);
+
+  for (int ie = 0; ie < nE; ++ie) {
+    const int32_t E = s.E[ie];
+    const int Q = crossmap_queries_per_lane(E, false);
+    const int64_t qt = (int64_t)kBlock * Q;
+    for (int it = 0; it < nT; ++it) {
+      const int32_t tau = s.tau[it];
+      const int64_t ne = N - (int64_t)(E - 1) * tau;
+      int64_t emb_off[2];
+      for (int sr = 0; sr < 2; ++sr) {
+        emb_off[sr] = p.n_emb;
+        p.embed.push_back({sr * N, p.n_emb, ne, E, tau});
+        p.n_emb += ne * E;
+        p.max_embed = std::max(p.max_embed, ne * E);
+      }
+      for (int il = 0; il < nL; ++il) {
+        const int64_t le = std::min(s.L[il], ne);
+        p.L_eff[((size_t)ie * nT + it) * nL + il] = le;
+        for (int ri = 0; ri < s.r; ++ri) {
+          const int64_t lib_off = p.n_lib;
+          p.sample.push_back({s.seed, ne, le, lib_off, E, tau, ri, 0});
+          p.n_lib += le;
+          for (int dir = 0; dir < 2; ++dir) {
+            // dir 0: library Y (series 1) predicts X (series 0); dir 1: reverse
+            const int lib_s = dir == 0 ? 1 : 0;
+            const int tgt_s = dir == 0 ? 0 : 1;
+            Realization R{};
+            R.emb_off = emb_off[lib_s];
+            R.lib_off = lib_off;
+            R.pts_off = p.n_pts;
+            R.tgt_off = tgt_s * N;
+            R.E = E;
+            R.tau = tau;
+            R.n_e = (int32_t)ne;
+            R.l_eff = (int32_t)le;
+            R.n_query = (int32_t)(s.query_set ? le : ne);
+            R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
+            R.slot_base = p.n_slots;
+            R.out_index = ((((int64_t)dir * nE + ie) * nT + it) * nL + il) * s.r + ri;
+            p.gather.push_back({R.emb_off, lib_off, p.n_pts, le, E, 0});
+            p.n_pts += le * E;
+            p.n_slots += R.n_tiles;
+            p.rz.push_back(R);
+            p.rz_sample.push_back((int64_t)p.sample.size() - 1);
+            // algorithmic work: every (query, candidate) pair but the query itself
+            const double nq = (double)R.n_query;
+            double pairs = nq * (double)le;
+            if (p.mode == kExclSelf) pairs -= s.query_set ? nq : (double)le;
+            p.pairs += pairs;
+            p.flops += pairs * (3.0 * E - 1.0);
+            p.preds += nq;
+          }
+        }
+      }
+    }
+  }
+  if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
+
+  // Items grouped by E; within a group the longest libraries go first.
+  std::vector<int32_t> order(p.rz.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (p.rz[a].E != p.rz[b].E) return p.rz[a].E < p.rz[b].E;
+    return p.rz[a].l_eff > p.rz[b].l_eff;
+  });
+  for (int32_t idx : order) {
+    const Realization& R = p.rz[idx];
+    if (p.e_count[R.E] == 0) p.e_first[R.E] = (int)p.items.size();
+    for (int t = 0; t < R.n_tiles; ++t) p.items.push_back({idx, t});
+    p.e_count[R.E] += R.n_tiles;
+  }
+  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
+
+  p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
+                   p.n_slots * sizeof(Moments) + p.n_out * 8 +
+                   p.rz.size() * sizeof(Realization) + p.items.size() * sizeof(Item) +
+                   p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// execution state of one plan
+// ---------------------------------------------------------------------------
+
+struct EvPair {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
+struct Exec {
+  Plan plan;
+  DevBuf d_ingest, d_embed, d_sample, d_gather, d_rz, d_items, d_plain_items;
+  DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_partial, d_out, d_counter;
+  std::vector<int64_t> plain_first;   // per realization: first plain item
+  hipGraphExec_t graph = nullptr;
+  ~Exec() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+struct ccm_ctx {
+  int device = 0;
+  int num_cus = 0;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  std::string err;
+  bool profiling = false;
+  std::vector<EvPair> ev_pending, ev_free;
+  ccm_profile prof{};
+  std::unique_ptr<Exec> exec;   // the most recent plan
+};
+
+namespace {
+
+EvPair take_events(ccm_ctx* c) {
+  if (!c->ev_free.empty()) {
+    EvPair e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  EvPair e;
+  HIPCHK(hipEventCreate(&e.a));
+  HIPCHK(hipEventCreate(&e.b));
+  return e;
+}
+
+void drain_events(ccm_ctx* c) {
+  for (EvPair& e : c->ev_pending) {
+    HIPCHK(hipEventSynchronize(e.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+    c->prof.kernel_ms += ms;
+    c->prof.launches += 1;
+    c->ev_free.push_back(e);
+  }
+  c->ev_pending.clear();
+}
+
+// Device buffers and descriptors for a plan (reused when the shape repeats).
+Exec* prepare(ccm_ctx* c, const Spec& s) {
+  if (c->exec && c->exec->plan.spec == s) return c->exec.get();
+  if (c->exec) {
+    // work queued earlier on any stream may still read the old buffers
+    HIPCHK(hipDeviceSynchronize());
+    c->exec.reset();   // free the previous plan's memory first
+  }
+  auto ex = std::make_unique<Exec>();
+  ex->plan = make_plan(s);
+  Plan& p = ex->plan;
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  if (p.device_bytes > free_b)
+    fail(CCM_E_NOMEM, "plan needs " + std::to_string(p.device_bytes) + " device bytes, " +
+                          std::to_string(free_b) + " free");
+  upload(ex->d_ingest, p.ingest);
+  upload(ex->d_embed, p.embed);
+  upload(ex->d_sample, p.sample);
+  upload(ex->d_gather, p.gather);
+  upload(ex->d_rz, p.rz);
+  upload(ex->d_items, p.items);
+  if (s.flags & CCM_FLAG_PLAIN) {
+    std::vector<Item> pi;
+    ex->plain_first.resize(p.rz.size());
+    for (size_t r = 0; r < p.rz.size(); ++r) {
+      ex->plain_first[r] = (int64_t)pi.size();
+      for (int t = 0; t < p.rz[r].n_tiles; ++t) pi.push_back({(int32_t)r, t});
+    }
+    upload(ex->d_plain_items, pi);
+  }
+  ex->d_s64.ensure(p.n64 * 8);
+  ex->d_s32.ensure(p.n32 * 4);
+  ex->d_emb.ensure(p.n_emb * 4);
+  ex->d_lib.ensure(p.n_lib * 4);
+  ex->d_pts.ensure(p.n_pts * 4);
+  ex->d_partial.ensure(p.n_slots * sizeof(Moments));
+  ex->d_out.ensure(p.n_out * 8);
+  ex->d_counter.ensure(64 * sizeof(int));
+  c->exec = std::move(ex);
+  return c->exec.get();
+}
+
+int persistent_grid(ccm_ctx* c, int n_items) {
+  // a few resident workgroups per CU; the queue balances the rest
+  const int g = std::max(1, c->num_cus) * 8;
+  return std::min(g, n_items);
+}
+
+// Queue every launch of a plan on stream st.
+void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
+  const Plan& p = ex->plan;
+  HIPCHK(launch_ingest(ex->d_ingest.as<IngestJob>(), (int)p.ingest.size(), p.n64,
+                       ex->d_s64.as<double>(), ex->d_s32.as<float>(), st));
+  HIPCHK(launch_embed(ex->d_embed.as<EmbedJob>(), (int)p.embed.size(), p.max_embed,
+                      ex->d_s32.as<float>(), ex->d_emb.as<float>(), st));
+  const bool plain = (p.spec.flags & CCM_FLAG_PLAIN) != 0;
+  const bool persistent = (p.spec.flags & CCM_FLAG_PERSISTENT) != 0;
+  const Dump nodump{nullptr, nullptr, nullptr};
+  if (!plain) {
+    HIPCHK(launch_sample(ex->d_sample.as<SampleJob>(), (int64_t)p.sample.size(),
+                         ex->d_lib.as<int32_t>(), st));
+    HIPCHK(launch_gather(ex->d_gather.as<GatherJob>(), (int64_t)p.gather.size(),
+                         ex->d_emb.as<float>(), ex->d_lib.as<int32_t>(),
+                         ex->d_pts.as<float>(), st));
+    for (int E = 1; E <= kMaxE; ++E) {
+      const int n = p.e_count[E];
+      if (n == 0) continue;
+      int grid = n;
+      int* next = nullptr;
+      if (persistent) {
+        grid = persistent_grid(c, n);
+        next = ex->d_counter.as<int>() + E;
+        HIPCHK(launch_zero_int(next, 1, st));
+      }
+      EvPair ev;
+      if (timed) {
+        ev = take_events(c);
+        HIPCHK(hipEventRecord(ev.a, st));
+      }
+      HIPCHK(launch_crossmap(E, p.mode, false, grid, ex->d_rz.as<Realization>(),
+                             ex->d_items.as<Item>() + p.e_first[E], n, next,
+                             ex->d_emb.as<float>(), ex->d_lib.as<int32_t>(),
+                             ex->d_pts.as<float>(), ex->d_s64.as<double>(),
+                             ex->d_partial.as<Moments>(), p.spec.query_set, p.window,
+                             nodump, st));
+      if (timed) {
+        HIPCHK(hipEventRecord(ev.b, st));
+        c->ev_pending.push_back(ev);
+      }
+    }
+  } else {
+    // the unbatched baseline: sampler, gather and cross-map launched per
+    // realization
+    for (size_t r = 0; r < p.rz.size(); ++r) {
+      const Realization& R = p.rz[r];
+      const int64_t sj = p.rz_sample[r];
+      if (r == 0 || p.rz_sample[r - 1] != sj)
+        HIPCHK(launch_sample(ex->d_sample.as<SampleJob>() + sj, 1, ex->d_lib.as<int32_t>(), st));
+      HIPCHK(launch_gather(ex->d_gather.as<GatherJob>() + r, 1, ex->d_emb.as<float>(),
+                           ex->d_lib.as<int32_t>(), ex->d_pts.as<float>(), st));
+      EvPair ev;
+      if (timed) {
+        ev = take_events(c);
+        HIPCHK(hipEventRecord(ev.a, st));
+      }
+      HIPCHK(launch_crossmap(R.E, p.mode, false, R.n_tiles, ex->d_rz.as<Realization>(),
+                             ex->d_plain_items.as<Item>() + ex->plain_first[r],
+                             R.n_tiles, nullptr, ex->d_emb.as<float>(),
+                             ex->d_lib.as<int32_t>(), ex->d_pts.as<float>(),
+                             ex->d_s64.as<double>(), ex->d_partial.as<Moments>(),
+                             p.spec.query_set, p.window, nodump, st));
+      if (timed) {
+        HIPCHK(hipEventRecord(ev.b, st));
+        c->ev_pending.push_back(ev);
+      }
+    }
+  }
+  HIPCHK(launch_finalize(ex->d_rz.as<Realization>(), (int64_t)p.rz.size(),
+                         ex->d_partial.as<Moments>(), ex->d_out.as<double>(), st));
+}
+
+// Run a prepared plan on stream st: series already in ex->d_s64.
+void run(ccm_ctx* c, Exec* ex, hipStream_t st) {
+  const Plan& p = ex->plan;
+  const bool use_graph = !c->profiling && !(p.spec.flags & CCM_FLAG_NO_GRAPH) &&
+                         !(p.spec.flags & CCM_FLAG_PLAIN);
+  if (use_graph) {
+    if (!ex->graph) {
+      hipStream_t cap = c->stream;
+      HIPCHK(hipStreamSynchronize(cap));
+      HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue(c, ex, cap, false);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamEndCapture(cap, &g));
+      hipError_t e = hipGraphInstantiate(&ex->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(e);
+    }
+    HIPCHK(hipGraphLaunch(ex->graph, st));
+  } else {
+    enqueue(c, ex, st, c->profiling);
+  }
+  if (c->profiling) {
+    c->prof.pairs += p.pairs;
+    c->prof.flops += p.flops;
+    c->prof.predictions += p.preds;
+    c->prof.realizations += (double)p.rz.size();
+  }
+}
+
+void check_host_series(const double* s, int64_t n, const char* name) {
+  if (!s) fail(CCM_E_INVAL, std::string(name) + " is NULL");
+  for (int64_t t = 0; t < n; ++t)
+    if (!std::isfinite(s[t]) || std::fabs(s[t]) > 1e17)
+      fail(CCM_E_INVAL, std::string(name) + " has a non-finite or too large value");
+}
+
+Spec make_spec(int64_t N, const int32_t* E, int32_t nE, const int32_t* tau, int32_t ntau,
+               const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
+               const ccm_opts* opts) {
+  if (!E || !tau || !L) fail(CCM_E_INVAL, "NULL parameter array");
+  if (nE < 1 || ntau < 1 || nL < 1) fail(CCM_E_INVAL, "nE, ntau and nL must be >= 1");
+  Spec s;
+  s.N = N;
+  s.E.assign(E, E + nE);
+  s.tau.assign(tau, tau + ntau);
+  s.L.assign(L, L + nL);
+  s.r = r;
+  s.seed = seed;
+  if (opts) {
+    s.excl = opts->exclusion_radius;
+    s.query_set = opts->query_set;
+    s.flags = opts->flags;
+  }
+  return s;
+}
+
+template <class F>
+ccm_status guarded(ccm_ctx* c, F&& f) {
+  if (!c) return CCM_E_INVAL;
+  std::lock_guard<std::mutex> lock(c->mu);
+  c->err.clear();
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    f();
+    return CCM_OK;
+  } catch (const Fail& e) {
+    c->err = e.what;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return CCM_E_NOMEM;
+  } catch (...) {
+    c->err = "unexpected error";
+    return CCM_E_DEVICE;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+ccm_status ccm_create(int device, ccm_ctx** out) {
+  if (!out) return CCM_E_INVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return CCM_E_DEVICE;
+  ccm_ctx* c = new (std::nothrow) ccm_ctx;
+  if (!c) return CCM_E_NOMEM;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&prop, device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return CCM_E_DEVICE;
+  }
+  c->num_cus = prop.multiProcessorCount;
+  *out = c;
+  return CCM_OK;
+}
+
+void ccm_destroy(ccm_ctx* c) {
+  if (!c) return;
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    c->exec.reset();
+    for (auto& e : c->ev_pending) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (auto& e : c->ev_free) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+const char* ccm_last_error(const ccm_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+ccm_status ccm_sweep(ccm_ctx* c, const double* X, const double* Y, int64_t N,
+                     const int32_t* E, int32_t nE, const int32_t* tau, int32_t ntau,
+                     const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
+                     const ccm_opts* opts, double* rho) {
+  return guarded(c, [&] {
+    if (!rho) fail(CCM_E_INVAL, "rho is NULL");
+    Spec s = make_spec(N, E, nE, tau, ntau, L, nL, r, seed, opts);
+    check_host_series(X, N, "X");
+    check_host_series(Y, N, "Y");
+    Exec* ex = prepare(c, s);
+    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>() + N, Y, N * 8, hipMemcpyHostToDevice, c->stream));
+    run(c, ex, c->stream);
+    HIPCHK(hipMemcpyAsync(rho, ex->d_out.p, ex->plan.n_out * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+ccm_status ccm(ccm_ctx* c, const double* X, const double* Y, int64_t N, int32_t E,
+               int32_t tau, const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
+               const ccm_opts* opts, double* rho_xy, double* rho_yx, int64_t* L_eff) {
+  return guarded(c, [&] {
+    if (!rho_xy || !rho_yx) fail(CCM_E_INVAL, "rho output is NULL");
+    Spec s = make_spec(N, &E, 1, &tau, 1, L, nL, r, seed, opts);
+    check_host_series(X, N, "X");
+    check_host_series(Y, N, "Y");
+    Exec* ex = prepare(c, s);
+    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>() + N, Y, N * 8, hipMemcpyHostToDevice, c->stream));
+    run(c, ex, c->stream);
+    const int64_t half = (int64_t)nL * r;
+    HIPCHK(hipMemcpyAsync(rho_xy, ex->d_out.p, half * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(rho_yx, ex->d_out.as<double>() + half, half * 8,
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (L_eff)
+      for (int i = 0; i < nL; ++i) L_eff[i] = ex->plan.L_eff[i];
+  });
+}
+
+ccm_status ccm_sweep_dev(ccm_ctx* c, const double* X, const double* Y, int64_t N,
+                         const int32_t* E, int32_t nE, const int32_t* tau, int32_t ntau,
+                         const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
+                         const ccm_opts* opts, double* rho, void* stream) {
+  return guarded(c, [&] {
+    if (!X || !Y || !rho) fail(CCM_E_INVAL, "NULL device pointer");
+    Spec s = make_spec(N, E, nE, tau, ntau, L, nL, r, seed, opts);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Exec* ex = prepare(c, s);
+    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>() + N, Y, N * 8, hipMemcpyDeviceToDevice, st));
+    run(c, ex, st);
+    HIPCHK(hipMemcpyAsync(rho, ex->d_out.p, ex->plan.n_out * 8, hipMemcpyDeviceToDevice, st));
+  });
+}
+
+ccm_status ccm_dev(ccm_ctx* c, const double* X, const double* Y, int64_t N, int32_t E,
+                   int32_t tau, const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
+                   const ccm_opts* opts, double* rho_xy, double* rho_yx, int64_t* L_eff,
+                   void* stream) {
+  return guarded(c, [&] {
+    if (!X || !Y || !rho_xy || !rho_yx) fail(CCM_E_INVAL, "NULL device pointer");
+    Spec s = make_spec(N, &E, 1, &tau, 1, L, nL, r, seed, opts);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Exec* ex = prepare(c, s);
+    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>() + N, Y, N * 8, hipMemcpyDeviceToDevice, st));
+    run(c, ex, st);
+    const int64_t half = (int64_t)nL * r;
+    HIPCHK(hipMemcpyAsync(rho_xy, ex->d_out.p, half * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(rho_yx, ex->d_out.as<double>() + half, half * 8,
+                          hipMemcpyDeviceToDevice, st));
+    if (L_eff)
+      for (int i = 0; i < nL; ++i) L_eff[i] = ex->plan.L_eff[i];
+  });
+}
+
+ccm_status ccm_library(ccm_ctx* c, int64_t N_e, int32_t E, int32_t tau, int64_t L_eff,
+                       int32_t r_index, uint64_t seed, int32_t* idx_out) {
+  return guarded(c, [&] {
+    if (!idx_out) fail(CCM_E_INVAL, "idx_out is NULL");
+    if (N_e < 1 || L_eff < 1 || L_eff > N_e || N_e > INT32_MAX)
+      fail(CCM_E_INVAL, "need 1 <= L_eff <= N_e < 2^31");
+    if (E < 1 || E > kMaxE || tau < 1) fail(CCM_E_INVAL, "E in [1, 10] and tau >= 1");
+    DevBuf job, out;
+    std::vector<SampleJob> j{{seed, N_e, L_eff, 0, E, tau, r_index, 0}};
+    upload(job, j);
+    out.ensure(L_eff * 4);
+    HIPCHK(launch_sample(job.as<SampleJob>(), 1, out.as<int32_t>(), c->stream));
+    HIPCHK(hipMemcpyAsync(idx_out, out.p, L_eff * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* target,
+                         int64_t N, int32_t E, int32_t tau, const int32_t* lib_idx,
+                         int64_t L_eff, const ccm_opts* opts, int32_t* nbr, float* d2,
+                         double* pred, double* rho) {
+  return guarded(c, [&] {
+    if (!lib_idx) fail(CCM_E_INVAL, "lib_idx is NULL");
+    if (N < 2 || N > INT32_MAX / 2) fail(CCM_E_INVAL, "N out of range");
+    if (E < 1 || E > kMaxE || tau < 1) fail(CCM_E_INVAL, "E in [1, 10] and tau >= 1");
+    check_host_series(lib_series, N, "lib_series");
+    check_host_series(target, N, "target");
+    const int64_t ne = N - (int64_t)(E - 1) * tau;
+    if (ne < E + 2) fail(CCM_E_INVAL, "N_e = N - (E-1) tau must be >= E + 2");
+    const int32_t excl = opts ? opts->exclusion_radius : 0;
+    const int32_t qs = opts ? opts->query_set : 0;
+    if (qs != 0 && qs != 1) fail(CCM_E_INVAL, "query_set must be 0 or 1");
+    if (L_eff < min_library(E, excl) || L_eff > ne)
+      fail(CCM_E_INVAL, "L_eff out of range for this E, tau and exclusion window");
+    for (int64_t i = 0; i < L_eff; ++i) {
+      if (lib_idx[i] < 0 || lib_idx[i] >= ne) fail(CCM_E_INVAL, "lib_idx out of range");
+      if (i > 0 && lib_idx[i] <= lib_idx[i - 1]) fail(CCM_E_INVAL, "lib_idx not ascending");
+    }
+    const int Q = crossmap_queries_per_lane(E, true);
+    const int64_t nq = qs ? L_eff : ne;
+    const int64_t qt = (int64_t)kBlock * Q;
+    const int n_tiles = (int)((nq + qt - 1) / qt);
+    const int K = E + 1;
+
+    DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_rz, d_items, d_ingest, d_embed, d_gather;
+    DevBuf d_partial, d_out, d_nbr, d_d2, d_pred;
+    d_s64.ensure(2 * N * 8);
+    HIPCHK(hipMemcpyAsync(d_s64.p, lib_series, N * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(d_s64.as<double>() + N, target, N * 8, hipMemcpyHostToDevice,
+                          c->stream));
+    d_s32.ensure(N * 4);
+    d_emb.ensure(ne * E * 4);
+    d_lib.ensure(L_eff * 4);
+    d_pts.ensure(L_eff * E * 4);
+    HIPCHK(hipMemcpyAsync(d_lib.p, lib_idx, L_eff * 4, hipMemcpyHostToDevice, c->stream));
+    std::vector<IngestJob> ij{{0, 0, N}};
+    std::vector<EmbedJob> ej{{0, 0, ne, E, tau}};
+    std::vector<GatherJob> gj{{0, 0, 0, L_eff, E, 0}};
+    Realization R{};
+    R.emb_off = 0;
+    R.lib_off = 0;
+    R.pts_off = 0;
+    R.tgt_off = N;
+    R.E = E;
+    R.tau = tau;
+    R.n_e = (int32_t)ne;
+    R.l_eff = (int32_t)L_eff;
+    R.n_query = (int32_t)nq;
+    R.n_tiles = n_tiles;
+    R.slot_base = 0;
+    R.out_index = 0;
+    std::vector<Realization> rv{R};
+    std::vector<Item> items;
+    for (int t = 0; t < n_tiles; ++t) items.push_back({0, t});
+    HIPCHK(hipStreamSynchronize(c->stream));
+    upload(d_ingest, ij);
+    upload(d_embed, ej);
+    upload(d_gather, gj);
+    upload(d_rz, rv);
+    upload(d_items, items);
+    d_partial.ensure(n_tiles * sizeof(Moments));
+    d_out.ensure(8);
+    d_nbr.ensure(nq * K * 4);
+    d_d2.ensure(nq * K * 4);
+    d_pred.ensure(nq * 8);
+    HIPCHK(launch_ingest(d_ingest.as<IngestJob>(), 1, N, d_s64.as<double>(),
+                         d_s32.as<float>(), c->stream));
+    HIPCHK(launch_embed(d_embed.as<EmbedJob>(), 1, ne * E, d_s32.as<float>(),
+                        d_emb.as<float>(), c->stream));
+    HIPCHK(launch_gather(d_gather.as<GatherJob>(), 1, d_emb.as<float>(), d_lib.as<int32_t>(),
+                         d_pts.as<float>(), c->stream));
+    Dump dump{d_nbr.as<int32_t>(), d_d2.as<float>(), d_pred.as<double>()};
+    HIPCHK(launch_crossmap(E, excl_mode(excl), true, n_tiles, d_rz.as<Realization>(),
+                           d_items.as<Item>(), n_tiles, nullptr, d_emb.as<float>(),
+                           d_lib.as<int32_t>(), d_pts.as<float>(), d_s64.as<double>(),
+                           d_partial.as<Moments>(), qs, excl > 0 ? excl : 0, dump,
+                           c->stream));
+    HIPCHK(launch_finalize(d_rz.as<Realization>(), 1, d_partial.as<Moments>(),
+                           d_out.as<double>(), c->stream));
+    if (nbr)
+      HIPCHK(hipMemcpyAsync(nbr, d_nbr.p, nq * K * 4, hipMemcpyDeviceToHost, c->stream));
+    if (d2) HIPCHK(hipMemcpyAsync(d2, d_d2.p, nq * K * 4, hipMemcpyDeviceToHost, c->stream));
+    if (pred)
+      HIPCHK(hipMemcpyAsync(pred, d_pred.p, nq * 8, hipMemcpyDeviceToHost, c->stream));
+    if (rho) HIPCHK(hipMemcpyAsync(rho, d_out.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+ccm_status ccm_profile_enable(ccm_ctx* c, int on) {
+  return guarded(c, [&] { c->profiling = on != 0; });
+}
+
+ccm_status ccm_profile_read(ccm_ctx* c, ccm_profile* out, int reset) {
+  return guarded(c, [&] {
+    if (!out) fail(CCM_E_INVAL, "out is NULL");
+    drain_events(c);
+    *out = c->prof;
+    if (reset) c->prof = ccm_profile{};
+  });
+}
+
+}  // extern "C"

@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--flags", type=int, default=0, help="CCM_FLAG_* bits")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample (0: skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB device to device "
+                         "once (a plain copy of known size for calibrating the "
+                         "profiler's byte counters)")
     return ap.parse_args()
 
 
@@ -118,6 +122,15 @@ def main():
     prof = ctx.profile_read(reset=True)
     el = t1 - t0
     print(f"bench: {a.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
+
+    if a.copy_mib > 0:
+        n = a.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     rh = rho.cpu().numpy()
     if not np.isfinite(rh).all():

@@ -23,11 +23,17 @@ struct IngestJob {
   int64_t n;
 };
 
-// One embedding: AoS float [n_e][E] with emb[i*E + k] = s[i + (E-1)tau - k tau].
+// One embedding of one series.
+//   emb[i*E + k] = s[i + (E-1)tau - k tau]           (AoS float [n_e][E])
+//   qord[p]      = embedded points in ascending order of their first
+//                  coordinate (the series value at their time)
 struct EmbedJob {
   int64_t src_off;   // floats into the FP32 series pool
   int64_t dst_off;   // floats into the embedding pool
+  int64_t order_off; // int32 into the series-order pool (n_series entries)
+  int64_t qord_off;  // int32 into the query-order pool (n_e entries)
   int64_t n_e;
+  int64_t n_series;
   int32_t E;
   int32_t tau;
 };
@@ -44,11 +50,33 @@ struct SampleJob {
   int32_t pad;
 };
 
+// One library gather: the library of one realization laid out in ascending
+// order of the first coordinate (pts AoS [l_eff][E], pj the embedded index
+// of each), plus the library position each query tile starts scanning from.
+struct GatherJob {
+  int64_t emb_off;   // floats: embedding of the library series
+  int64_t lib_off;   // int32: library indices (ascending index order)
+  int64_t order_off; // int32: order of the library series' values
+  int64_t pts_off;   // floats: output coordinates
+  int64_t pj_off;    // int32: output embedded indices
+  int64_t start_off; // int32: output scan start per query tile
+  int64_t l_eff;
+  int64_t n_e;
+  int64_t n_series;
+  int32_t E;
+  int32_t tau;
+  int32_t qt;        // queries per tile
+  int32_t query_set; // 0: every embedded point is a query
+  int32_t sorted;    // 0: keep ascending index order (no series order)
+  int32_t pad;
+};
+
 // One realization: a library drawn over one embedding, predicting one target.
 struct Realization {
   int64_t emb_off;   // floats: AoS embedding of the library series
-  int64_t lib_off;   // int32: library indices (ascending)
-  int64_t pts_off;   // floats: library coordinates gathered, AoS [l_eff][E]
+  int64_t pts_off;   // floats: ordered library coordinates, AoS [l_eff][E]
+  int64_t pj_off;    // int32: ordered library embedded indices
+  int64_t qord_off;  // int32: query order of the embedding
   int64_t tgt_off;   // doubles: FP64 target series (time 0)
   int32_t E;
   int32_t tau;
@@ -56,18 +84,8 @@ struct Realization {
   int32_t l_eff;     // library size
   int32_t n_query;   // queries: n_e, or l_eff when only library points are queried
   int32_t n_tiles;   // query tiles (= work items) of this realization
-  int64_t slot_base; // first partial-moment slot (one per tile)
+  int64_t slot_base; // first partial-moment slot (one per tile; also scan starts)
   int64_t out_index; // where rho goes in the caller's output
-};
-
-// One library gather: pts[c*E + k] = emb[lib[c]*E + k] for c < l_eff.
-struct GatherJob {
-  int64_t emb_off;
-  int64_t lib_off;
-  int64_t pts_off;
-  int64_t l_eff;
-  int32_t E;
-  int32_t pad;
 };
 
 // A work item: one query tile of one realization.
@@ -81,11 +99,11 @@ struct Moments {
   double n, mt, mp, m2t, m2p, c;
 };
 
-// Optional per-query dump (test hook): neighbours, squared distances, predictions.
+// Optional per-query dump (test hook), rows indexed by embedded point.
 struct Dump {
-  int32_t* nbr;   // [n_query][E+1]
-  float* d2;      // [n_query][E+1]
-  double* pred;   // [n_query]
+  int32_t* nbr;   // [n_e][E+1]
+  float* d2;      // [n_e][E+1]
+  double* pred;   // [n_e]
 };
 
 // Launchers (defined with the kernels).
@@ -94,18 +112,35 @@ hipError_t launch_ingest(const IngestJob* jobs, int n_jobs, int64_t max_n,
                          const double* src, float* dst, hipStream_t st);
 hipError_t launch_embed(const EmbedJob* jobs, int n_jobs, int64_t max_n,
                         const float* s32, float* emb, hipStream_t st);
+hipError_t launch_iota_segments(int32_t* out, int64_t n_series, int32_t segs,
+                                hipStream_t st);
+hipError_t launch_query_order(const EmbedJob* jobs, int n_jobs,
+                              const int32_t* order, int32_t* qord, hipStream_t st);
 hipError_t launch_sample(const SampleJob* jobs, int64_t n_jobs, int32_t* out,
                          hipStream_t st);
-hipError_t launch_gather(const GatherJob* jobs, int64_t n_jobs, const float* emb,
-                         const int32_t* lib, float* pts, hipStream_t st);
+hipError_t launch_gather(const GatherJob* jobs, int64_t n_jobs, int64_t max_n_e,
+                         const float* emb, const int32_t* lib, const int32_t* order,
+                         float* pts, int32_t* pj, int32_t* start, hipStream_t st);
 hipError_t launch_zero_int(int* p, int n, hipStream_t st);
 hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
                            const Realization* rzs, const Item* items,
                            int n_items, int* next, const float* emb,
-                           const int32_t* lib, const float* pts,
+                           const float* pts, const int32_t* pj,
+                           const int32_t* qord, const int32_t* start,
                            const double* tgt, Moments* partial, int query_set,
                            int window, Dump d, hipStream_t st);
 hipError_t launch_finalize(const Realization* rzs, int64_t n_rz,
                            const Moments* partial, double* out, hipStream_t st);
+
+// Series value order (ccm_sort.hip): per segment of n_series values, the
+// time indices sorted by value (stable).  temp_bytes is queried with
+// temp == nullptr.
+hipError_t sort_series(void* temp, size_t& temp_bytes, const float* keys_in,
+                       float* keys_out, const int32_t* idx_in, int32_t* idx_out,
+                       int64_t n_series, int32_t segs, const int32_t* seg_offsets,
+                       hipStream_t st);
+
+// Largest embedding whose membership bitmask fits the gather kernel's LDS.
+int64_t gather_max_sorted_n_e();
 
 }  // namespace ccmk

@@ -8,19 +8,27 @@
 // library size L (Introduction).
 //
 // Kernels, in pipeline order:
-//   k_ingest     double series -> float series (round to nearest even)
-//   k_embed      lagged-coordinate embedding, AoS float[n_e][E]
-//   k_sample     library subsamples: selection sampling driven by SplitMix64
-//   k_crossmap   fused distance / top-(E+1) / prediction / Pearson moments,
-//                one workgroup per (realization, query tile) work item,
-//                optionally persistent with an atomic work queue
-//   k_finalize   merge the per-tile moments of each realization -> rho
+//   k_ingest       double series -> float series (round to nearest even)
+//   k_embed        lagged-coordinate embedding, AoS float[n_e][E]
+//   (sort_series)  each series' time indices in ascending order of value
+//   k_query_order  embedded points in ascending order of first coordinate
+//   k_sample       library subsamples: selection sampling driven by SplitMix64
+//   k_gather       each library laid out in first-coordinate order, plus the
+//                  position every query tile starts scanning from
+//   k_crossmap     fused distance / top-(E+1) / prediction / Pearson moments,
+//                  one workgroup per (realization, query tile) work item,
+//                  optionally persistent with an atomic work queue
+//   k_finalize     merge the per-tile moments of each realization -> rho
 //
 // Arithmetic that must agree bit for bit with the CPU oracle:
 //   d2 = sum_k (q_k - p_k)^2 in binary32 as acc = fma(diff, diff, acc),
 //   k ascending from acc = +0 (the first term is the plain product, which is
 //   the same value), no other contraction (-ffp-contract=off);
 //   neighbours are the first E+1 candidates in (d2, j) order.
+// The order in which candidates are visited is free: selection uses the exact
+// (d2, j) key.  Queries are grouped and candidates visited nearest first (in
+// the first coordinate) only so that the running lists settle early and the
+// insertion path stays rare; every (query, candidate) pair is still evaluated.
 #include "ccm_internal.h"
 
 namespace ccmk {
@@ -52,6 +60,58 @@ __global__ void k_embed(const EmbedJob* __restrict__ jobs,
     const int64_t i = x / J.E;
     const int k = (int)(x - i * J.E);
     o[x] = s[i + (int64_t)(J.E - 1 - k) * J.tau];
+  }
+}
+
+// Time indices 0..n-1 for every series segment (input of the value sort).
+__global__ void k_iota_segments(int32_t* __restrict__ out, int64_t n, int64_t total) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total;
+       x += (int64_t)gridDim.x * blockDim.x)
+    out[x] = (int32_t)(x % n);
+}
+
+// Exclusive rank of this thread among the flagged threads of its 256-thread
+// workgroup, and the workgroup total, in thread order.
+__device__ __forceinline__ int block_rank(bool flag, int* s_wave, int& total) {
+  const uint64_t m = __builtin_amdgcn_ballot_w64(flag);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int r = __popcll(m & lt);
+  if (lane == 0) s_wave[wave] = __popcll(m);
+  __syncthreads();
+  int before = 0;
+  total = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const int c = s_wave[w];
+    if (w < wave) before += c;
+    total += c;
+  }
+  __syncthreads();
+  return before + r;
+}
+
+// Embedded points in ascending order of their first coordinate: the series
+// order restricted to times >= (E-1) tau, shifted to embedded indices.
+// One workgroup per embedding.
+__global__ __launch_bounds__(kBlock) void k_query_order(
+    const EmbedJob* __restrict__ jobs, const int32_t* __restrict__ order_pool,
+    int32_t* __restrict__ qord_pool) {
+  __shared__ int s_wave[kBlock / 64];
+  const EmbedJob J = jobs[blockIdx.x];
+  const int32_t* __restrict__ ord = order_pool + J.order_off;
+  int32_t* __restrict__ q = qord_pool + J.qord_off;
+  const int64_t off = (int64_t)(J.E - 1) * J.tau;
+  int64_t out = 0;
+  for (int64_t base = 0; base < J.n_series; base += kBlock) {
+    const int64_t k = base + threadIdx.x;
+    const int64_t t = k < J.n_series ? ord[k] : -1;
+    const bool f = t >= off;
+    int total;
+    const int r = block_rank(f, s_wave, total);
+    if (f) q[out + r] = (int32_t)(t - off);
+    out += total;
   }
 }
 
@@ -97,22 +157,79 @@ __global__ void k_sample(const SampleJob* __restrict__ jobs, int64_t n_jobs,
   for (; s < J.l_eff; ++s, ++j) out[s] = (int32_t)j;
 }
 
-// Library coordinates laid out contiguously per realization, so the scan
-// streams them through the scalar cache with no dependent index load.
-// One workgroup per job.
-__global__ void k_gather(const GatherJob* __restrict__ jobs,
-                         const float* __restrict__ emb_pool,
-                         const int32_t* __restrict__ lib_pool,
-                         float* __restrict__ pts_pool) {
+// The library of one realization, laid out contiguously in ascending order
+// of the first coordinate (coordinates AoS and embedded indices), so the scan
+// streams it through the scalar cache with no dependent index load.  For each
+// query tile (tiles take consecutive queries in the same order) it records
+// the library position of the tile's middle query: the scan starts there and
+// works outward.  One workgroup per job; the library's membership bitmask
+// lives in LDS (dynamic size).  Jobs marked unsorted keep ascending index
+// order and start every tile at position 0.
+__global__ __launch_bounds__(kBlock) void k_gather(
+    const GatherJob* __restrict__ jobs, const float* __restrict__ emb_pool,
+    const int32_t* __restrict__ lib_pool, const int32_t* __restrict__ order_pool,
+    float* __restrict__ pts_pool, int32_t* __restrict__ pj_pool,
+    int32_t* __restrict__ start_pool) {
+  extern __shared__ uint32_t bits[];
+  __shared__ int s_wave[2][kBlock / 64];
   const GatherJob J = jobs[blockIdx.x];
   const float* __restrict__ emb = emb_pool + J.emb_off;
   const int32_t* __restrict__ lib = lib_pool + J.lib_off;
   float* __restrict__ pts = pts_pool + J.pts_off;
-  const int64_t n = J.l_eff * J.E;
-  for (int64_t x = threadIdx.x; x < n; x += blockDim.x) {
-    const int64_t c = x / J.E;
-    const int k = (int)(x - c * J.E);
-    pts[x] = emb[(int64_t)lib[c] * J.E + k];
+  int32_t* __restrict__ pj = pj_pool + J.pj_off;
+  int32_t* __restrict__ start = start_pool + J.start_off;
+  const int E = J.E;
+  const int tid = threadIdx.x;
+
+  if (!J.sorted) {
+    for (int64_t x = tid; x < J.l_eff * E; x += kBlock) {
+      const int64_t c = x / E;
+      const int k = (int)(x - c * E);
+      pts[x] = emb[(int64_t)lib[c] * E + k];
+    }
+    for (int64_t c = tid; c < J.l_eff; c += kBlock) pj[c] = lib[c];
+    if (J.query_set == 0) {
+      const int64_t tiles = (J.n_e + J.qt - 1) / J.qt;
+      for (int64_t t = tid; t < tiles; t += kBlock) start[t] = 0;
+    }
+    return;
+  }
+
+  const int64_t nw = (J.n_e + 31) / 32;
+  for (int64_t w = tid; w < nw; w += kBlock) bits[w] = 0u;
+  __syncthreads();
+  for (int64_t c = tid; c < J.l_eff; c += kBlock) {
+    const int32_t j = lib[c];
+    atomicOr(&bits[j >> 5], 1u << (j & 31));
+  }
+  __syncthreads();
+
+  const int32_t* __restrict__ ord = order_pool + J.order_off;
+  const int64_t off = (int64_t)(E - 1) * J.tau;
+  int64_t pf = 0;   // embedded points passed so far (in order)
+  int64_t pl = 0;   // library points passed so far (in order)
+  for (int64_t base = 0; base < J.n_series; base += kBlock) {
+    const int64_t k = base + tid;
+    const int64_t t = k < J.n_series ? ord[k] : -1;
+    const bool fo = t >= off;
+    const int64_t i = fo ? t - off : 0;
+    const bool fl = fo && ((bits[i >> 5] >> (i & 31)) & 1u);
+    int tot_o, tot_l;
+    const int ro = block_rank(fo, s_wave[0], tot_o);
+    const int rl = block_rank(fl, s_wave[1], tot_l);
+    if (fl) {
+      const int64_t c = pl + rl;
+      pj[c] = (int32_t)i;
+      for (int kk = 0; kk < E; ++kk) pts[c * E + kk] = emb[i * E + kk];
+    }
+    if (fo && J.query_set == 0) {
+      const int64_t p = pf + ro;
+      const int64_t tile = p / J.qt;
+      const int64_t anchor = min(tile * J.qt + J.qt / 2, J.n_e - 1);
+      if (p == anchor) start[tile] = (int32_t)(pl + rl);
+    }
+    pf += tot_o;
+    pl += tot_l;
   }
 }
 
@@ -120,12 +237,12 @@ __global__ void k_gather(const GatherJob* __restrict__ jobs,
 // candidate keys
 // ---------------------------------------------------------------------------
 //
-// A candidate (d2, c) is kept as one 64-bit word: high half the binary32 bits
-// of d2, low half its position c in the library.  Library indices ascend
-// with position, so (d2, c) orders exactly like (d2, j).  For d2 >= 0 the
-// bit patterns of binary32 order like the values, so the word read as an
-// unsigned integer orders exactly like (d2, c) lexicographically.  The same word read as a binary64 is a
-// non-negative number (denormal when d2 is 0 or tiny, never NaN: the high
+// A candidate (d2, j) is kept as one 64-bit word: high half the binary32 bits
+// of d2, low half its embedded index j.  For d2 >= 0 the bit patterns of
+// binary32 order like the values, so the word read as an unsigned integer
+// orders exactly like (d2, j) lexicographically.  The same word read as a
+// binary64 is a non-negative number (denormal when d2 is 0 or tiny, never
+// NaN: the high
 // exponent field is at most 0x7f8), and non-negative binary64 values also
 // order like their bit patterns -- so the FP64 min/max units keep a sorted
 // list of keys, two instructions per slot.  FP64 denormals are preserved in
@@ -221,21 +338,27 @@ struct Group {
   static constexpr int G = E <= 2 ? 8 : (E <= 4 ? 4 : 2);
 };
 
+template <int E, int MODE>
+struct Slots {
+  static constexpr int KS = MODE == kExclSelf ? E + 2 : E + 1;
+};
+
+// Distances from the lane's queries to library positions c..c+G-1, then one
+// compare per query against its running (KS)-th best; only when some lane
+// of the wavefront qualifies are the candidates inserted.
 template <int E, int Q, int MODE, int G>
 __device__ __forceinline__ void scan_group(
-    const float* __restrict__ pts, const int32_t* __restrict__ lib, int c,
+    const float* __restrict__ pts, const int32_t* __restrict__ pj, int c,
     const float (&qc)[Q][E], const int (&qi)[Q], int window,
-    double (&key)[Q][MODE == kExclSelf ? E + 2 : E + 1]) {
-  constexpr int KS = MODE == kExclSelf ? E + 2 : E + 1;
+    double (&key)[Q][Slots<E, MODE>::KS]) {
+  constexpr int KS = Slots<E, MODE>::KS;
   float p[G][E];
+  int32_t j[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g)
+  for (int g = 0; g < G; ++g) {
 #pragma unroll
     for (int k = 0; k < E; ++k) p[g][k] = pts[(int64_t)(c + g) * E + k];
-  int32_t jw[G];
-  if (MODE == kWindow) {
-#pragma unroll
-    for (int g = 0; g < G; ++g) jw[g] = lib[c + g];
+    j[g] = pj[c + g];
   }
   float d2[G][Q];
 #pragma unroll
@@ -244,13 +367,11 @@ __device__ __forceinline__ void scan_group(
     for (int m = 0; m < Q; ++m) {
       float v = sqdist<E>(qc[m], p[g]);
       if (MODE == kWindow) {
-        const int dj = jw[g] - qi[m];
+        const int dj = j[g] - qi[m];
         if (dj <= window && dj >= -window) v = __builtin_nanf("");
       }
       d2[g][m] = v;
     }
-  // One compare per query per group: the group minimum against the current
-  // (KS)-th best; only then, and only for lanes that qualify, insert.
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
     float mn = d2[0][m];
@@ -260,7 +381,7 @@ __device__ __forceinline__ void scan_group(
 #pragma unroll
       for (int g = 0; g < G; ++g)
         if (d2[g][m] <= key_d2(key[m][KS - 1]))
-          insert_key<KS>(key[m], make_key(d2[g][m], c + g));
+          insert_key<KS>(key[m], make_key(d2[g][m], j[g]));
     }
   }
 }
@@ -268,28 +389,32 @@ __device__ __forceinline__ void scan_group(
 template <int E, int Q, int MODE, bool DUMP>
 __device__ __forceinline__ void crossmap_item(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
-    const int32_t* __restrict__ lib_pool, const float* __restrict__ pts_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
     const double* __restrict__ tgt_pool, Moments* __restrict__ partial,
     int query_set, int window, const Dump& dump, Moments* red) {
   constexpr int K = E + 1;                          // neighbours (Section 3.2)
-  constexpr int KS = MODE == kExclSelf ? K + 1 : K; // running slots
+  constexpr int KS = Slots<E, MODE>::KS;            // running slots
   constexpr int G = Group<E>::G;
+  constexpr int QT = kBlock * Q;                    // queries per tile
   const int tid = threadIdx.x;
   const float* __restrict__ emb = emb_pool + R.emb_off;
-  const int32_t* __restrict__ lib = lib_pool + R.lib_off;
   const float* __restrict__ pts = pts_pool + R.pts_off;
+  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
+  const int32_t* __restrict__ qord = qord_pool + R.qord_off;
   const double* __restrict__ tgt = tgt_pool + R.tgt_off;
   const int64_t off = (int64_t)(E - 1) * R.tau;     // time of embedded point 0
   const int L = R.l_eff;
 
-  // queries of this lane: tile*QT + m*kBlock + tid
+  // queries of this lane: positions tile*QT + m*kBlock + tid of the query
+  // order (every embedded point, or the ordered library itself)
   float qc[Q][E];
   int qi[Q];
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
-    const int qq = tile * (kBlock * Q) + m * kBlock + tid;
+    const int qq = tile * QT + m * kBlock + tid;
     const bool valid = qq < R.n_query;
-    const int i = valid ? (query_set ? lib[qq] : qq) : 0;
+    const int i = valid ? (query_set ? pj[qq] : qord[qq]) : 0;
     qi[m] = valid ? i : -1;
 #pragma unroll
     for (int k = 0; k < E; ++k) qc[m][k] = emb[(int64_t)i * E + k];
@@ -301,45 +426,53 @@ __device__ __forceinline__ void crossmap_item(
 #pragma unroll
     for (int s = 0; s < KS; ++s) key[m][s] = empty_key();
 
-  // Brute-force scan of the library in ascending position (= index) order.
-  int c = 0;
-  for (; c + G <= L; c += G)
-    scan_group<E, Q, MODE, G>(pts, lib, c, qc, qi, window, key);
-  for (; c < L; ++c)
-    scan_group<E, Q, MODE, 1>(pts, lib, c, qc, qi, window, key);
+  // Brute-force scan of every library position, outward from the tile's
+  // start: groups alternate forward [f, f+G) and backward [b-G, b); single
+  // positions finish both ends.
+  int s0 = query_set ? min(tile * QT + QT / 2, L - 1) : start_pool[R.slot_base + tile];
+  s0 = min(max(s0, 0), L);
+  int f = s0, b = s0;
+  bool fwd = true;
+  for (;;) {
+    const bool can_f = f + G <= L;
+    const bool can_b = b - G >= 0;
+    if (!can_f && !can_b) break;
+    const bool take_f = can_f && (fwd || !can_b);
+    const int c = take_f ? f : b - G;
+    if (take_f) f += G;
+    else b -= G;
+    fwd = !fwd;
+    scan_group<E, Q, MODE, G>(pts, pj, c, qc, qi, window, key);
+  }
+  for (; f < L; ++f) scan_group<E, Q, MODE, 1>(pts, pj, f, qc, qi, window, key);
+  for (; b > 0; --b) scan_group<E, Q, MODE, 1>(pts, pj, b - 1, qc, qi, window, key);
 
   // Simplex projection from the E+1 neighbours, then Pearson moments.
   Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
     if (qi[m] < 0) continue;
-    // every slot holds a real candidate (the library has at least KS of
-    // them); positions are clamped all the same before indexing
-    int32_t jj[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int pos = min(max(key_j(key[m][s]), 0), L - 1);
-      jj[s] = lib[pos];
-    }
     float nd[K];
     int32_t nj[K];
     if (MODE == kExclSelf) {
-      // the query itself is at most one of the KS keys; without it the
+      // the query itself is at most one of the KS keys (every slot holds a
+      // real candidate: the library has at least KS points); without it the
       // first K of the others are the neighbours
       int pos = KS - 1;
 #pragma unroll
       for (int s = KS - 1; s >= 0; --s)
-        if (jj[s] == qi[m]) pos = s;
+        if (key_j(key[m][s]) == qi[m]) pos = s;
 #pragma unroll
       for (int t = 0; t < K; ++t) {
-        nd[t] = key_d2(t < pos ? key[m][t] : key[m][t + 1]);
-        nj[t] = t < pos ? jj[t] : jj[t + 1];
+        const double kk = t < pos ? key[m][t] : key[m][t + 1];
+        nd[t] = key_d2(kk);
+        nj[t] = key_j(kk);
       }
     } else {
 #pragma unroll
       for (int t = 0; t < K; ++t) {
         nd[t] = key_d2(key[m][t]);
-        nj[t] = jj[t];
+        nj[t] = key_j(key[m][t]);
       }
     }
     double dist[K], u[K];
@@ -360,13 +493,13 @@ __device__ __forceinline__ void crossmap_item(
     for (int t = 0; t < K; ++t) pred += (u[t] / su) * tgt[nj[t] + off];
     mom_add(mo, tgt[qi[m] + off], pred);
     if (DUMP) {
-      const int64_t qq = (int64_t)tile * (kBlock * Q) + m * kBlock + tid;
+      const int64_t row = qi[m];
 #pragma unroll
       for (int t = 0; t < K; ++t) {
-        dump.nbr[qq * K + t] = nj[t];
-        dump.d2[qq * K + t] = nd[t];
+        dump.nbr[row * K + t] = nj[t];
+        dump.d2[row * K + t] = nd[t];
       }
-      dump.pred[qq] = pred;
+      dump.pred[row] = pred;
     }
   }
 
@@ -390,7 +523,8 @@ template <int E, int Q, int MODE, bool DUMP>
 __global__ __launch_bounds__(kBlock) void k_crossmap(
     const Realization* __restrict__ rzs, const Item* __restrict__ items,
     int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
-    const int32_t* __restrict__ lib_pool, const float* __restrict__ pts_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
     const double* __restrict__ tgt_pool, Moments* __restrict__ partial,
     int query_set, int window, Dump dump) {
   __shared__ Moments red[kBlock];
@@ -399,9 +533,9 @@ __global__ __launch_bounds__(kBlock) void k_crossmap(
   while (it < n_items) {
     const Item I = items[it];
     const Realization R = rzs[I.rz];
-    crossmap_item<E, Q, MODE, DUMP>(R, I.tile, emb_pool, lib_pool, pts_pool,
-                                    tgt_pool, partial, query_set, window, dump,
-                                    red);
+    crossmap_item<E, Q, MODE, DUMP>(R, I.tile, emb_pool, pts_pool, pj_pool,
+                                    qord_pool, start_pool, tgt_pool, partial,
+                                    query_set, window, dump, red);
     if (next == nullptr) {
       it += gridDim.x;
     } else {
@@ -438,8 +572,9 @@ __global__ void k_finalize(const Realization* __restrict__ rzs, int64_t n_rz,
 // ---------------------------------------------------------------------------
 
 using CrossmapFn = void (*)(const Realization*, const Item*, int, int*,
-                            const float*, const int32_t*, const float*,
-                            const double*, Moments*, int, int, Dump);
+                            const float*, const float*, const int32_t*,
+                            const int32_t*, const int32_t*, const double*,
+                            Moments*, int, int, Dump);
 
 template <int E, int Q>
 struct QSet {
@@ -515,6 +650,21 @@ hipError_t launch_embed(const EmbedJob* jobs, int n_jobs, int64_t max_n,
   return hipGetLastError();
 }
 
+hipError_t launch_iota_segments(int32_t* out, int64_t n_series, int32_t segs,
+                                hipStream_t st) {
+  const int64_t total = n_series * segs;
+  if (total <= 0) return hipSuccess;
+  k_iota_segments<<<blocks_for(total, 256), 256, 0, st>>>(out, n_series, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_order(const EmbedJob* jobs, int n_jobs,
+                              const int32_t* order, int32_t* qord, hipStream_t st) {
+  if (n_jobs <= 0) return hipSuccess;
+  k_query_order<<<n_jobs, kBlock, 0, st>>>(jobs, order, qord);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample(const SampleJob* jobs, int64_t n_jobs, int32_t* out,
                          hipStream_t st) {
   if (n_jobs <= 0) return hipSuccess;
@@ -523,10 +673,21 @@ hipError_t launch_sample(const SampleJob* jobs, int64_t n_jobs, int32_t* out,
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const GatherJob* jobs, int64_t n_jobs, const float* emb,
-                         const int32_t* lib, float* pts, hipStream_t st) {
+// Membership bitmasks up to 48 KiB of LDS per workgroup.
+static constexpr int64_t kGatherBitmaskWords = 12 * 1024;
+
+int64_t gather_max_sorted_n_e() { return kGatherBitmaskWords * 32; }
+
+hipError_t launch_gather(const GatherJob* jobs, int64_t n_jobs, int64_t max_n_e,
+                         const float* emb, const int32_t* lib, const int32_t* order,
+                         float* pts, int32_t* pj, int32_t* start, hipStream_t st) {
   if (n_jobs <= 0) return hipSuccess;
-  k_gather<<<(unsigned)n_jobs, 256, 0, st>>>(jobs, emb, lib, pts);
+  // max_n_e covers the jobs marked sorted; larger ones must be unsorted
+  int64_t words = (max_n_e + 31) / 32;
+  if (words > kGatherBitmaskWords) return hipErrorInvalidValue;
+  if (words < 1) words = 1;
+  k_gather<<<(unsigned)n_jobs, kBlock, (size_t)words * 4, st>>>(jobs, emb, lib, order,
+                                                                 pts, pj, start);
   return hipGetLastError();
 }
 
@@ -539,15 +700,16 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
 hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
                            const Realization* rzs, const Item* items,
                            int n_items, int* next, const float* emb,
-                           const int32_t* lib, const float* pts,
+                           const float* pts, const int32_t* pj,
+                           const int32_t* qord, const int32_t* start,
                            const double* tgt, Moments* partial, int query_set,
                            int window, Dump d, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   CrossmapFn f = crossmap_kernel(E, mode, dump, nullptr);
   if (!f) return hipErrorInvalidValue;
   hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), 0, st, rzs, items,
-                     n_items, next, emb, lib, pts, tgt, partial, query_set,
-                     window, d);
+                     n_items, next, emb, pts, pj, qord, start, tgt, partial,
+                     query_set, window, d);
   return hipGetLastError();
 }
 

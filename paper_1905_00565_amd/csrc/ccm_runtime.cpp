@@ -120,10 +120,16 @@ struct Plan {
   int64_t n64 = 0, n32 = 0;
   std::vector<EmbedJob> embed;
   int64_t n_emb = 0, max_embed = 0;
+  int64_t n_qord = 0;                 // query-order entries (sum of n_e)
+  int32_t n_series = 2;               // series sorted (segments)
+  std::vector<int32_t> seg_off;       // segment offsets of the value sort
+  size_t sort_temp = 0;
   std::vector<SampleJob> sample;
   int64_t n_lib = 0;
   std::vector<GatherJob> gather;
-  int64_t n_pts = 0;
+  int64_t n_pts = 0;                  // floats of ordered library coordinates
+  int64_t n_pj = 0;                   // ordered library indices
+  int64_t max_sorted_n_e = 0;
   std::vector<Realization> rz;
   // realization r owns sample job rz_sample[r] and gather job r
   std::vector<int64_t> rz_sample;
@@ -169,6 +175,9 @@ Plan make_plan(const Spec& s) {
   p.n64 = 2 * N;
   p.n32 = 2 * N;
   p.ingest.push_back({0, 0, 2 * N});
+  p.n_series = 2;
+  p.seg_off = {0, (int32_t)N, (int32_t)(2 * N)};
+  const int64_t sorted_limit = gather_max_sorted_n_e();
   p.n_out = 2LL * nE * nT * nL * s.r;
   p.L_eff.assign((size_t)nE * nT * nL, 0);
 
@@ -179,13 +188,17 @@ Plan make_plan(const Spec& s) {
     for (int it = 0; it < nT; ++it) {
       const int32_t tau = s.tau[it];
       const int64_t ne = N - (int64_t)(E - 1) * tau;
-      int64_t emb_off[2];
+      int64_t emb_off[2], qord_off[2];
       for (int sr = 0; sr < 2; ++sr) {
         emb_off[sr] = p.n_emb;
-        p.embed.push_back({sr * N, p.n_emb, ne, E, tau});
+        qord_off[sr] = p.n_qord;
+        p.embed.push_back({sr * N, p.n_emb, sr * N, p.n_qord, ne, N, E, tau});
         p.n_emb += ne * E;
+        p.n_qord += ne;
         p.max_embed = std::max(p.max_embed, ne * E);
       }
+      const int32_t sorted = ne <= sorted_limit ? 1 : 0;
+      if (sorted) p.max_sorted_n_e = std::max(p.max_sorted_n_e, ne);
       for (int il = 0; il < nL; ++il) {
         const int64_t le = std::min(s.L[il], ne);
         p.L_eff[((size_t)ie * nT + it) * nL + il] = le;
@@ -199,8 +212,9 @@ Plan make_plan(const Spec& s) {
             const int tgt_s = dir == 0 ? 0 : 1;
             Realization R{};
             R.emb_off = emb_off[lib_s];
-            R.lib_off = lib_off;
             R.pts_off = p.n_pts;
+            R.pj_off = p.n_pj;
+            R.qord_off = qord_off[lib_s];
             R.tgt_off = tgt_s * N;
             R.E = E;
             R.tau = tau;
@@ -210,8 +224,24 @@ Plan make_plan(const Spec& s) {
             R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
             R.slot_base = p.n_slots;
             R.out_index = ((((int64_t)dir * nE + ie) * nT + it) * nL + il) * s.r + ri;
-            p.gather.push_back({R.emb_off, lib_off, p.n_pts, le, E, 0});
+            GatherJob gj{};
+            gj.emb_off = R.emb_off;
+            gj.lib_off = lib_off;
+            gj.order_off = lib_s * N;
+            gj.pts_off = R.pts_off;
+            gj.pj_off = R.pj_off;
+            gj.start_off = R.slot_base;
+            gj.l_eff = le;
+            gj.n_e = ne;
+            gj.n_series = N;
+            gj.E = E;
+            gj.tau = tau;
+            gj.qt = (int32_t)qt;
+            gj.query_set = s.query_set;
+            gj.sorted = sorted;
+            p.gather.push_back(gj);
             p.n_pts += le * E;
+            p.n_pj += le;
             p.n_slots += R.n_tiles;
             p.rz.push_back(R);
             p.rz_sample.push_back((int64_t)p.sample.size() - 1);
@@ -244,7 +274,11 @@ Plan make_plan(const Spec& s) {
   }
   if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
 
+  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
+                     p.n_series, nullptr, nullptr));
   p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
+                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 + p.sort_temp +
+                   (size_t)p.n32 * 12 +
                    p.n_slots * sizeof(Moments) + p.n_out * 8 +
                    p.rz.size() * sizeof(Realization) + p.items.size() * sizeof(Item) +
                    p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
@@ -262,7 +296,8 @@ struct EvPair {
 struct Exec {
   Plan plan;
   DevBuf d_ingest, d_embed, d_sample, d_gather, d_rz, d_items, d_plain_items;
-  DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_partial, d_out, d_counter;
+  DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_pj, d_partial, d_out, d_counter;
+  DevBuf d_iota, d_keys_out, d_order, d_segoff, d_sort_temp, d_qord, d_start;
   std::vector<int64_t> plain_first;   // per realization: first plain item
   hipGraphExec_t graph = nullptr;
   ~Exec() {
@@ -345,11 +380,19 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
     }
     upload(ex->d_plain_items, pi);
   }
+  upload(ex->d_segoff, p.seg_off);
   ex->d_s64.ensure(p.n64 * 8);
   ex->d_s32.ensure(p.n32 * 4);
+  ex->d_iota.ensure(p.n32 * 4);
+  ex->d_keys_out.ensure(p.n32 * 4);
+  ex->d_order.ensure(p.n32 * 4);
+  ex->d_sort_temp.ensure(p.sort_temp);
+  ex->d_qord.ensure(p.n_qord * 4);
+  ex->d_start.ensure(p.n_slots * 4);
   ex->d_emb.ensure(p.n_emb * 4);
   ex->d_lib.ensure(p.n_lib * 4);
   ex->d_pts.ensure(p.n_pts * 4);
+  ex->d_pj.ensure(p.n_pj * 4);
   ex->d_partial.ensure(p.n_slots * sizeof(Moments));
   ex->d_out.ensure(p.n_out * 8);
   ex->d_counter.ensure(64 * sizeof(int));
@@ -370,6 +413,15 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                        ex->d_s64.as<double>(), ex->d_s32.as<float>(), st));
   HIPCHK(launch_embed(ex->d_embed.as<EmbedJob>(), (int)p.embed.size(), p.max_embed,
                       ex->d_s32.as<float>(), ex->d_emb.as<float>(), st));
+  HIPCHK(launch_iota_segments(ex->d_iota.as<int32_t>(), p.spec.N, p.n_series, st));
+  {
+    size_t tb = p.sort_temp;
+    HIPCHK(sort_series(ex->d_sort_temp.p, tb, ex->d_s32.as<float>(), ex->d_keys_out.as<float>(),
+                       ex->d_iota.as<int32_t>(), ex->d_order.as<int32_t>(), p.spec.N,
+                       p.n_series, ex->d_segoff.as<int32_t>(), st));
+  }
+  HIPCHK(launch_query_order(ex->d_embed.as<EmbedJob>(), (int)p.embed.size(),
+                            ex->d_order.as<int32_t>(), ex->d_qord.as<int32_t>(), st));
   const bool plain = (p.spec.flags & CCM_FLAG_PLAIN) != 0;
   const bool persistent = (p.spec.flags & CCM_FLAG_PERSISTENT) != 0;
   const Dump nodump{nullptr, nullptr, nullptr};
@@ -377,8 +429,9 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
     HIPCHK(launch_sample(ex->d_sample.as<SampleJob>(), (int64_t)p.sample.size(),
                          ex->d_lib.as<int32_t>(), st));
     HIPCHK(launch_gather(ex->d_gather.as<GatherJob>(), (int64_t)p.gather.size(),
-                         ex->d_emb.as<float>(), ex->d_lib.as<int32_t>(),
-                         ex->d_pts.as<float>(), st));
+                         p.max_sorted_n_e, ex->d_emb.as<float>(), ex->d_lib.as<int32_t>(),
+                         ex->d_order.as<int32_t>(), ex->d_pts.as<float>(),
+                         ex->d_pj.as<int32_t>(), ex->d_start.as<int32_t>(), st));
     for (int E = 1; E <= kMaxE; ++E) {
       const int n = p.e_count[E];
       if (n == 0) continue;
@@ -396,8 +449,9 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
       }
       HIPCHK(launch_crossmap(E, p.mode, false, grid, ex->d_rz.as<Realization>(),
                              ex->d_items.as<Item>() + p.e_first[E], n, next,
-                             ex->d_emb.as<float>(), ex->d_lib.as<int32_t>(),
-                             ex->d_pts.as<float>(), ex->d_s64.as<double>(),
+                             ex->d_emb.as<float>(), ex->d_pts.as<float>(),
+                             ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
+                             ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
                              ex->d_partial.as<Moments>(), p.spec.query_set, p.window,
                              nodump, st));
       if (timed) {
@@ -413,8 +467,11 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
       const int64_t sj = p.rz_sample[r];
       if (r == 0 || p.rz_sample[r - 1] != sj)
         HIPCHK(launch_sample(ex->d_sample.as<SampleJob>() + sj, 1, ex->d_lib.as<int32_t>(), st));
-      HIPCHK(launch_gather(ex->d_gather.as<GatherJob>() + r, 1, ex->d_emb.as<float>(),
-                           ex->d_lib.as<int32_t>(), ex->d_pts.as<float>(), st));
+      HIPCHK(launch_gather(ex->d_gather.as<GatherJob>() + r, 1,
+                           p.gather[r].sorted ? p.gather[r].n_e : 0, ex->d_emb.as<float>(),
+                           ex->d_lib.as<int32_t>(), ex->d_order.as<int32_t>(),
+                           ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
+                           ex->d_start.as<int32_t>(), st));
       EvPair ev;
       if (timed) {
         ev = take_events(c);
@@ -423,7 +480,8 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
       HIPCHK(launch_crossmap(R.E, p.mode, false, R.n_tiles, ex->d_rz.as<Realization>(),
                              ex->d_plain_items.as<Item>() + ex->plain_first[r],
                              R.n_tiles, nullptr, ex->d_emb.as<float>(),
-                             ex->d_lib.as<int32_t>(), ex->d_pts.as<float>(),
+                             ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
+                             ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
                              ex->d_s64.as<double>(), ex->d_partial.as<Moments>(),
                              p.spec.query_set, p.window, nodump, st));
       if (timed) {
@@ -689,25 +747,28 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     const int64_t qt = (int64_t)kBlock * Q;
     const int n_tiles = (int)((nq + qt - 1) / qt);
     const int K = E + 1;
+    const int32_t sorted = ne <= gather_max_sorted_n_e() ? 1 : 0;
 
-    DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_rz, d_items, d_ingest, d_embed, d_gather;
-    DevBuf d_partial, d_out, d_nbr, d_d2, d_pred;
-    d_s64.ensure(2 * N * 8);
-    HIPCHK(hipMemcpyAsync(d_s64.p, lib_series, N * 8, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(d_s64.as<double>() + N, target, N * 8, hipMemcpyHostToDevice,
-                          c->stream));
-    d_s32.ensure(N * 4);
-    d_emb.ensure(ne * E * 4);
-    d_lib.ensure(L_eff * 4);
-    d_pts.ensure(L_eff * E * 4);
-    HIPCHK(hipMemcpyAsync(d_lib.p, lib_idx, L_eff * 4, hipMemcpyHostToDevice, c->stream));
+    DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_pj, d_rz, d_items, d_ingest, d_embed,
+        d_gather, d_partial, d_out, d_nbr, d_d2, d_pred, d_iota, d_keys_out, d_order,
+        d_segoff, d_temp, d_qord, d_start;
+    std::vector<int32_t> seg{0, (int32_t)N};
+    size_t temp_bytes = 0;
+    HIPCHK(sort_series(nullptr, temp_bytes, nullptr, nullptr, nullptr, nullptr, N, 1,
+                       nullptr, nullptr));
     std::vector<IngestJob> ij{{0, 0, N}};
-    std::vector<EmbedJob> ej{{0, 0, ne, E, tau}};
-    std::vector<GatherJob> gj{{0, 0, 0, L_eff, E, 0}};
+    std::vector<EmbedJob> ej{{0, 0, 0, 0, ne, N, E, tau}};
+    GatherJob g{};
+    g.l_eff = L_eff;
+    g.n_e = ne;
+    g.n_series = N;
+    g.E = E;
+    g.tau = tau;
+    g.qt = (int32_t)qt;
+    g.query_set = qs;
+    g.sorted = sorted;
+    std::vector<GatherJob> gj{g};
     Realization R{};
-    R.emb_off = 0;
-    R.lib_off = 0;
-    R.pts_off = 0;
     R.tgt_off = N;
     R.E = E;
     R.tau = tau;
@@ -715,43 +776,72 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     R.l_eff = (int32_t)L_eff;
     R.n_query = (int32_t)nq;
     R.n_tiles = n_tiles;
-    R.slot_base = 0;
-    R.out_index = 0;
     std::vector<Realization> rv{R};
     std::vector<Item> items;
     for (int t = 0; t < n_tiles; ++t) items.push_back({0, t});
-    HIPCHK(hipStreamSynchronize(c->stream));
+    upload(d_segoff, seg);
     upload(d_ingest, ij);
     upload(d_embed, ej);
     upload(d_gather, gj);
     upload(d_rz, rv);
     upload(d_items, items);
+    d_s64.ensure(2 * N * 8);
+    d_s32.ensure(N * 4);
+    d_iota.ensure(N * 4);
+    d_keys_out.ensure(N * 4);
+    d_order.ensure(N * 4);
+    d_temp.ensure(temp_bytes);
+    d_qord.ensure(ne * 4);
+    d_start.ensure(n_tiles * 4);
+    d_emb.ensure(ne * E * 4);
+    d_lib.ensure(L_eff * 4);
+    d_pts.ensure(L_eff * E * 4);
+    d_pj.ensure(L_eff * 4);
     d_partial.ensure(n_tiles * sizeof(Moments));
     d_out.ensure(8);
-    d_nbr.ensure(nq * K * 4);
-    d_d2.ensure(nq * K * 4);
-    d_pred.ensure(nq * 8);
+    // dump rows are indexed by embedded point
+    d_nbr.ensure(ne * K * 4);
+    d_d2.ensure(ne * K * 4);
+    d_pred.ensure(ne * 8);
+    hipStream_t st = c->stream;
+    HIPCHK(hipMemcpyAsync(d_s64.p, lib_series, N * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_s64.as<double>() + N, target, N * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_lib.p, lib_idx, L_eff * 4, hipMemcpyHostToDevice, st));
     HIPCHK(launch_ingest(d_ingest.as<IngestJob>(), 1, N, d_s64.as<double>(),
-                         d_s32.as<float>(), c->stream));
+                         d_s32.as<float>(), st));
     HIPCHK(launch_embed(d_embed.as<EmbedJob>(), 1, ne * E, d_s32.as<float>(),
-                        d_emb.as<float>(), c->stream));
-    HIPCHK(launch_gather(d_gather.as<GatherJob>(), 1, d_emb.as<float>(), d_lib.as<int32_t>(),
-                         d_pts.as<float>(), c->stream));
+                        d_emb.as<float>(), st));
+    HIPCHK(launch_iota_segments(d_iota.as<int32_t>(), N, 1, st));
+    HIPCHK(sort_series(d_temp.p, temp_bytes, d_s32.as<float>(), d_keys_out.as<float>(),
+                       d_iota.as<int32_t>(), d_order.as<int32_t>(), N, 1,
+                       d_segoff.as<int32_t>(), st));
+    HIPCHK(launch_query_order(d_embed.as<EmbedJob>(), 1, d_order.as<int32_t>(),
+                              d_qord.as<int32_t>(), st));
+    HIPCHK(launch_gather(d_gather.as<GatherJob>(), 1, sorted ? ne : 0, d_emb.as<float>(),
+                         d_lib.as<int32_t>(), d_order.as<int32_t>(), d_pts.as<float>(),
+                         d_pj.as<int32_t>(), d_start.as<int32_t>(), st));
     Dump dump{d_nbr.as<int32_t>(), d_d2.as<float>(), d_pred.as<double>()};
     HIPCHK(launch_crossmap(E, excl_mode(excl), true, n_tiles, d_rz.as<Realization>(),
                            d_items.as<Item>(), n_tiles, nullptr, d_emb.as<float>(),
-                           d_lib.as<int32_t>(), d_pts.as<float>(), d_s64.as<double>(),
-                           d_partial.as<Moments>(), qs, excl > 0 ? excl : 0, dump,
-                           c->stream));
+                           d_pts.as<float>(), d_pj.as<int32_t>(), d_qord.as<int32_t>(),
+                           d_start.as<int32_t>(), d_s64.as<double>(),
+                           d_partial.as<Moments>(), qs, excl > 0 ? excl : 0, dump, st));
     HIPCHK(launch_finalize(d_rz.as<Realization>(), 1, d_partial.as<Moments>(),
-                           d_out.as<double>(), c->stream));
-    if (nbr)
-      HIPCHK(hipMemcpyAsync(nbr, d_nbr.p, nq * K * 4, hipMemcpyDeviceToHost, c->stream));
-    if (d2) HIPCHK(hipMemcpyAsync(d2, d_d2.p, nq * K * 4, hipMemcpyDeviceToHost, c->stream));
-    if (pred)
-      HIPCHK(hipMemcpyAsync(pred, d_pred.p, nq * 8, hipMemcpyDeviceToHost, c->stream));
-    if (rho) HIPCHK(hipMemcpyAsync(rho, d_out.p, 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+                           d_out.as<double>(), st));
+    std::vector<int32_t> hn(ne * K);
+    std::vector<float> hd(ne * K);
+    std::vector<double> hp(ne);
+    HIPCHK(hipMemcpyAsync(hn.data(), d_nbr.p, ne * K * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hd.data(), d_d2.p, ne * K * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hp.data(), d_pred.p, ne * 8, hipMemcpyDeviceToHost, st));
+    if (rho) HIPCHK(hipMemcpyAsync(rho, d_out.p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t q = 0; q < nq; ++q) {
+      const int64_t row = qs ? lib_idx[q] : q;
+      if (nbr) std::memcpy(nbr + q * K, hn.data() + row * K, K * 4);
+      if (d2) std::memcpy(d2 + q * K, hd.data() + row * K, K * 4);
+      if (pred) pred[q] = hp[row];
+    }
   });
 }
 

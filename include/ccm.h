@@ -134,8 +134,25 @@ ccm_status ccm_sweep(ccm_ctx *ctx, const double *X, const double *Y,
                      const ccm_opts *opts, double *rho);
 
 /*
- * Device-pointer forms: X, Y (double[N]) and rho are device pointers, the
- * other arrays are host pointers; the work is queued on `stream` (a
+ * Causal matrix over M series (Introduction: unidirectional and
+ * bidirectional links between variables; every ordered pair is a
+ * cross map).  One neighbour search on the manifold of series a serves the
+ * prediction of every other series b (the library draw does not depend on
+ * the series).
+ *   S           host double[M][N], row-major
+ *   rho         host double[M][M][nL][r]: rho[a][b] is the skill of
+ *               predicting series b from the manifold of series a (high when
+ *               b drives a); the diagonal is NaN
+ * Requires M >= 2; other rules as for ccm().
+ */
+ccm_status ccm_matrix(ccm_ctx *ctx, const double *S, int32_t M, int64_t N,
+                      int32_t E, int32_t tau, const int64_t *L, int32_t nL,
+                      int32_t r, uint64_t seed, const ccm_opts *opts,
+                      double *rho);
+
+/*
+ * Device-pointer forms: X, Y (double[N]), S (double[M][N]) and rho are
+ * device pointers, the other arrays are host pointers; the work is queued on `stream` (a
  * hipStream_t; NULL = the null stream) and the call returns without waiting.
  * Output layouts as above.
  */
@@ -149,6 +166,10 @@ ccm_status ccm_sweep_dev(ccm_ctx *ctx, const double *X, const double *Y,
                          const int32_t *tau, int32_t ntau, const int64_t *L,
                          int32_t nL, int32_t r, uint64_t seed,
                          const ccm_opts *opts, double *rho, void *stream);
+ccm_status ccm_matrix_dev(ccm_ctx *ctx, const double *S, int32_t M, int64_t N,
+                          int32_t E, int32_t tau, const int64_t *L, int32_t nL,
+                          int32_t r, uint64_t seed, const ccm_opts *opts,
+                          double *rho, void *stream);
 
 /*
  * Test hook: the library subsample the sampler draws for realization

@@ -82,6 +82,9 @@ class Oracle:
         L.oracle_neighbors.argtypes = [P, P, i64, i32, i32, P, i64, i32, i32,
                                        P, P, P, P]
         L.oracle_neighbors.restype = C.c_int
+        L.oracle_neighbors_at.argtypes = [P, P, i64, i32, i32, P, i64, i32, P, i64,
+                                          P, P, P]
+        L.oracle_neighbors_at.restype = C.c_int
         L.oracle_realization.argtypes = [P, P, i64, i32, i32, i64, i32, u64,
                                          i32, i32, P, P]
         L.oracle_realization.restype = C.c_int
@@ -134,6 +137,20 @@ class Oracle:
                                               len(li), excl, query_set, _ptr(nbr),
                                               _ptr(d2), _ptr(pred), C.byref(rho)))
         return nbr[:nq], d2[:nq], pred[:nq], rho.value
+
+    def neighbors_at(self, S, T, E, tau, lib_idx, queries, excl=0):
+        """(nbr [nq][E+1], d2 [nq][E+1], pred [nq]) at the listed embedded queries."""
+        S, T = _f64(S), _f64(T)
+        li = np.ascontiguousarray(lib_idx, dtype=np.int32)
+        qs = np.ascontiguousarray(queries, dtype=np.int64)
+        nq = len(qs)
+        nbr = np.empty((max(nq, 1), E + 1), dtype=np.int32)
+        d2 = np.empty((max(nq, 1), E + 1), dtype=np.float32)
+        pred = np.empty(max(nq, 1), dtype=np.float64)
+        self._check(self.lib.oracle_neighbors_at(_ptr(S), _ptr(T), len(S), E, tau, _ptr(li),
+                                                 len(li), excl, _ptr(qs), nq, _ptr(nbr),
+                                                 _ptr(d2), _ptr(pred)))
+        return nbr[:nq], d2[:nq], pred[:nq]
 
     def realization(self, S, T, E, tau, L, r_index, seed, excl=0, query_set=0):
         """(rho, L_eff) of one sampled realization."""

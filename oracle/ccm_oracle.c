@@ -207,6 +207,32 @@ static int excluded(int64_t i, int64_t j, int32_t excl)
 }
 
 /*
+ * Neighbours and prediction of one query i: scan every library candidate,
+ * keep the first k = E+1 in (d2, j) order, predict T at t_i.
+ * Returns 0, or OR_EINVAL if fewer than k candidates remain.
+ */
+static int one_query(const float *Sf, const double *T, int32_t E, int32_t tau,
+                     int64_t off, const int32_t *lib, int64_t L_eff, int32_t excl,
+                     int64_t i, cand_t *best, double *pred)
+{
+    const int k = E + 1;
+    int n = 0;
+    for (int64_t c = 0; c < L_eff; ++c) {
+        const int64_t j = lib[c];
+        if (excluded(i, j, excl))
+            continue;
+        cand_t cd;
+        cd.d2 = sqdist_f32(Sf, i + off, j + off, E, tau);
+        cd.j = (int32_t)j;
+        keep_smallest(best, &n, k, cd);
+    }
+    if (n < k)
+        return OR_EINVAL;
+    *pred = simplex_predict(best, k, T, off);
+    return OR_OK;
+}
+
+/*
  * One realization: library series S (manifold), target T, library indices
  * lib[0..L_eff-1] (embedded-point indices).  Queries are every embedded point
  * (query_set 0) or the library points themselves (query_set 1).  For each
@@ -242,31 +268,63 @@ int oracle_neighbors(const double *S, const double *T, int64_t N, int32_t E,
     for (int64_t q = 0; q < Nq; ++q) {
         const int64_t i = query_set ? lib[q] : q;
         cand_t best[11];
-        int n = 0;
-        for (int64_t c = 0; c < L_eff; ++c) {
-            const int64_t j = lib[c];
-            if (excluded(i, j, excl))
-                continue;
-            cand_t cd;
-            cd.d2 = sqdist_f32(Sf, i + off, j + off, E, tau);
-            cd.j = (int32_t)j;
-            keep_smallest(best, &n, k, cd);
-        }
-        if (n < k) {
-            status = OR_EINVAL;
+        status = one_query(Sf, T, E, tau, off, lib, L_eff, excl, i, best, &P[q]);
+        if (status != OR_OK)
             break;
-        }
         for (int m = 0; m < k; ++m) {
             if (nbr) nbr[q * k + m] = best[m].j;
             if (d2) d2[q * k + m] = best[m].d2;
         }
-        P[q] = simplex_predict(best, k, T, off);
         O[q] = T[i + off];
         if (pred) pred[q] = P[q];
     }
     if (status == OR_OK && rho)
         *rho = oracle_pearson(O, P, Nq);
     free(Sf); free(P); free(O);
+    return status;
+}
+
+/*
+ * The same per-query results for an explicit list of queries (embedded
+ * indices), without the skill: lets a large realization be checked at sampled
+ * queries.  Outputs are [nq][E+1] and [nq].
+ */
+int oracle_neighbors_at(const double *S, const double *T, int64_t N, int32_t E,
+                        int32_t tau, const int32_t *lib, int64_t L_eff,
+                        int32_t excl, const int64_t *queries, int64_t nq,
+                        int32_t *nbr, float *d2, double *pred)
+{
+    if (!S || !T || !lib || !queries || N < 2 || E < 1 || E > 10 || tau < 1)
+        return OR_EINVAL;
+    const int64_t off = (int64_t)(E - 1) * tau;
+    const int64_t Ne = N - off;
+    if (Ne < 2 || L_eff < 1 || L_eff > Ne)
+        return OR_EINVAL;
+    const int k = E + 1;
+    float *Sf = (float *)malloc(sizeof(float) * (size_t)N);
+    if (!Sf)
+        return OR_ENOMEM;
+    for (int64_t t = 0; t < N; ++t)
+        Sf[t] = (float)S[t];
+    int status = OR_OK;
+    for (int64_t q = 0; q < nq; ++q) {
+        const int64_t i = queries[q];
+        if (i < 0 || i >= Ne) {
+            status = OR_EINVAL;
+            break;
+        }
+        cand_t best[11];
+        double p = 0.0;
+        status = one_query(Sf, T, E, tau, off, lib, L_eff, excl, i, best, &p);
+        if (status != OR_OK)
+            break;
+        for (int m = 0; m < k; ++m) {
+            if (nbr) nbr[q * k + m] = best[m].j;
+            if (d2) d2[q * k + m] = best[m].d2;
+        }
+        if (pred) pred[q] = p;
+    }
+    free(Sf);
     return status;
 }
 

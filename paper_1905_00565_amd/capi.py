@@ -33,7 +33,8 @@ CCM_FLAG_PERSISTENT = 4
 # Every symbol include/ccm.h declares (checked by the ABI test).
 EXPORTS = [
     "ccm_create", "ccm_destroy", "ccm_last_error", "ccm", "ccm_sweep",
-    "ccm_dev", "ccm_sweep_dev", "ccm_library", "ccm_neighbors",
+    "ccm_matrix", "ccm_dev", "ccm_sweep_dev", "ccm_matrix_dev", "ccm_library",
+    "ccm_neighbors",
     "ccm_profile_enable", "ccm_profile_read",
 ]
 
@@ -82,6 +83,8 @@ def lib():
         L.ccm_sweep.argtypes = [P, P, P, i64, P, i32, P, i32, P, i32, i32, u64, P, P]
         L.ccm_dev.argtypes = [P, P, P, i64, i32, i32, P, i32, i32, u64, P, P, P, P, P]
         L.ccm_sweep_dev.argtypes = [P, P, P, i64, P, i32, P, i32, P, i32, i32, u64, P, P, P]
+        L.ccm_matrix.argtypes = [P, P, i32, i64, i32, i32, P, i32, i32, u64, P, P]
+        L.ccm_matrix_dev.argtypes = [P, P, i32, i64, i32, i32, P, i32, i32, u64, P, P, P]
         L.ccm_library.argtypes = [P, i64, i32, i32, i64, i32, u64, P]
         L.ccm_neighbors.argtypes = [P, P, P, i64, i32, i32, P, i64, P, P, P, P, P]
         L.ccm_profile_enable.argtypes = [P, C.c_int]
@@ -206,6 +209,32 @@ def ccm_sweep_dev(ctx, X, Y, E, tau, L, r, seed, rho, stream=None,
                                     _stream_ptr(stream)))
 
 
+def ccm_matrix(ctx, S, E, tau, L, r, seed, exclusion_radius=0, query_set=0, flags=0):
+    """rho [M][M][nL][r]: rho[a][b] predicts series b from the manifold of a."""
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    if S.ndim != 2:
+        raise ValueError("S must be [M][N]")
+    M, N = S.shape
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    rho = np.empty((M, M, len(Ls), r))
+    o = _opts(exclusion_radius, query_set, flags)
+    _check(ctx, lib().ccm_matrix(ctx, _ptr(S), M, N, E, tau, _ptr(Ls), len(Ls), r,
+                                 seed & (2**64 - 1), C.byref(o), _ptr(rho)))
+    return rho
+
+
+def ccm_matrix_dev(ctx, S, E, tau, L, r, seed, rho, stream=None, exclusion_radius=0,
+                   query_set=0, flags=0, M=None, N=None):
+    """Device form of ccm_matrix: S is a device double[M][N], rho double[M][M][nL][r]."""
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    m = int(M if M is not None else S.shape[0])
+    n = int(N if N is not None else S.shape[1])
+    o = _opts(exclusion_radius, query_set, flags)
+    _check(ctx, lib().ccm_matrix_dev(ctx, _dev_ptr(S), m, n, E, tau, _ptr(Ls), len(Ls), r,
+                                     seed & (2**64 - 1), C.byref(o), _dev_ptr(rho),
+                                     _stream_ptr(stream)))
+
+
 def ccm_library(ctx, N_e, E, tau, L_eff, r_index, seed):
     out = np.empty(max(int(L_eff), 1), dtype=np.int32)
     _check(ctx, lib().ccm_library(ctx, N_e, E, tau, L_eff, r_index, seed & (2**64 - 1),
@@ -276,6 +305,12 @@ class Context:
 
     def ccm_sweep_dev(self, *a, **k):
         return ccm_sweep_dev(self.handle, *a, **k)
+
+    def ccm_matrix(self, *a, **k):
+        return ccm_matrix(self.handle, *a, **k)
+
+    def ccm_matrix_dev(self, *a, **k):
+        return ccm_matrix_dev(self.handle, *a, **k)
 
     def ccm_library(self, *a, **k):
         return ccm_library(self.handle, *a, **k)

@@ -132,6 +132,20 @@ hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
 hipError_t launch_finalize(const Realization* rzs, int64_t n_rz,
                            const Moments* partial, double* out, hipStream_t st);
 
+// Causal-matrix form: one neighbour search per realization predicts every
+// series; self_of[rz] is the searched series (its own target is skipped).
+// partial holds one record of multi_sums_bytes() per (item slot, series).
+hipError_t launch_crossmap_multi(int E, int mode, int grid, const Realization* rzs,
+                                 const int32_t* self_of, const Item* items, int n_items,
+                                 int* next, const float* emb, const float* pts,
+                                 const int32_t* pj, const int32_t* qord, const int32_t* start,
+                                 const double* tgt, int64_t n_series, int m_series,
+                                 void* partial, int query_set, int window, hipStream_t st);
+hipError_t launch_finalize_multi(const Realization* rzs, const int32_t* self_of,
+                                 int64_t n_rz, int m_series, const void* partial,
+                                 int64_t out_stride_b, double* out, hipStream_t st);
+size_t multi_sums_bytes();
+
 // Series value order (ccm_sort.hip): per segment of n_series values, the
 // time indices sorted by value (stable).  temp_bytes is queried with
 // temp == nullptr.

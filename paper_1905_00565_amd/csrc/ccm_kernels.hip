@@ -386,15 +386,22 @@ __device__ __forceinline__ void scan_group(
   }
 }
 
-template <int E, int Q, int MODE, bool DUMP>
-__device__ __forceinline__ void crossmap_item(
+// Queries of one item and their running candidate lists after the scan of
+// the whole library.
+template <int E, int Q, int MODE>
+struct ScanState {
+  float qc[Q][E];
+  int qi[Q];
+  double key[Q][Slots<E, MODE>::KS];
+};
+
+template <int E, int Q, int MODE>
+__device__ __forceinline__ void scan_library(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
     const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tgt_pool, Moments* __restrict__ partial,
-    int query_set, int window, const Dump& dump, Moments* red) {
-  constexpr int K = E + 1;                          // neighbours (Section 3.2)
-  constexpr int KS = Slots<E, MODE>::KS;            // running slots
+    int query_set, int window, ScanState<E, Q, MODE>& S) {
+  constexpr int KS = Slots<E, MODE>::KS;
   constexpr int G = Group<E>::G;
   constexpr int QT = kBlock * Q;                    // queries per tile
   const int tid = threadIdx.x;
@@ -402,29 +409,23 @@ __device__ __forceinline__ void crossmap_item(
   const float* __restrict__ pts = pts_pool + R.pts_off;
   const int32_t* __restrict__ pj = pj_pool + R.pj_off;
   const int32_t* __restrict__ qord = qord_pool + R.qord_off;
-  const double* __restrict__ tgt = tgt_pool + R.tgt_off;
-  const int64_t off = (int64_t)(E - 1) * R.tau;     // time of embedded point 0
   const int L = R.l_eff;
 
   // queries of this lane: positions tile*QT + m*kBlock + tid of the query
   // order (every embedded point, or the ordered library itself)
-  float qc[Q][E];
-  int qi[Q];
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
     const int qq = tile * QT + m * kBlock + tid;
     const bool valid = qq < R.n_query;
     const int i = valid ? (query_set ? pj[qq] : qord[qq]) : 0;
-    qi[m] = valid ? i : -1;
+    S.qi[m] = valid ? i : -1;
 #pragma unroll
-    for (int k = 0; k < E; ++k) qc[m][k] = emb[(int64_t)i * E + k];
+    for (int k = 0; k < E; ++k) S.qc[m][k] = emb[(int64_t)i * E + k];
   }
-
-  double key[Q][KS];
 #pragma unroll
   for (int m = 0; m < Q; ++m)
 #pragma unroll
-    for (int s = 0; s < KS; ++s) key[m][s] = empty_key();
+    for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
 
   // Brute-force scan of every library position, outward from the tile's
   // start: groups alternate forward [f, f+G) and backward [b-G, b); single
@@ -442,58 +443,94 @@ __device__ __forceinline__ void crossmap_item(
     if (take_f) f += G;
     else b -= G;
     fwd = !fwd;
-    scan_group<E, Q, MODE, G>(pts, pj, c, qc, qi, window, key);
+    scan_group<E, Q, MODE, G>(pts, pj, c, S.qc, S.qi, window, S.key);
   }
-  for (; f < L; ++f) scan_group<E, Q, MODE, 1>(pts, pj, f, qc, qi, window, key);
-  for (; b > 0; --b) scan_group<E, Q, MODE, 1>(pts, pj, b - 1, qc, qi, window, key);
+  for (; f < L; ++f) scan_group<E, Q, MODE, 1>(pts, pj, f, S.qc, S.qi, window, S.key);
+  for (; b > 0; --b) scan_group<E, Q, MODE, 1>(pts, pj, b - 1, S.qc, S.qi, window, S.key);
+}
+
+// The E+1 neighbours of query m (nearest first) from its running list.
+template <int E, int Q, int MODE>
+__device__ __forceinline__ void select_neighbors(const ScanState<E, Q, MODE>& S, int m,
+                                                 float (&nd)[E + 1], int32_t (&nj)[E + 1]) {
+  constexpr int K = E + 1;
+  constexpr int KS = Slots<E, MODE>::KS;
+  if (MODE == kExclSelf) {
+    // the query itself is at most one of the KS keys (every slot holds a
+    // real candidate: the library has at least KS points); without it the
+    // first K of the others are the neighbours
+    int pos = KS - 1;
+#pragma unroll
+    for (int s = KS - 1; s >= 0; --s)
+      if (key_j(S.key[m][s]) == S.qi[m]) pos = s;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const double kk = t < pos ? S.key[m][t] : S.key[m][t + 1];
+      nd[t] = key_d2(kk);
+      nj[t] = key_j(kk);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      nd[t] = key_d2(S.key[m][t]);
+      nj[t] = key_j(S.key[m][t]);
+    }
+  }
+}
+
+// Simplex-projection weights (Section 2.1): d = sqrt(d2) in double,
+// u = exp(-d / d_1) (or the zero-distance rule when d_1 = 0), w = u / sum u.
+template <int K>
+__device__ __forceinline__ void simplex_weights(const float (&nd)[K], double (&w)[K]) {
+  double dist[K], u[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) dist[t] = sqrt((double)nd[t]);
+  if (dist[0] > 0.0) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) u[t] = exp(-dist[t] / dist[0]);
+  } else {
+#pragma unroll
+    for (int t = 0; t < K; ++t) u[t] = dist[t] == 0.0 ? 1.0 : 0.0;
+  }
+  double su = 0.0;
+#pragma unroll
+  for (int t = 0; t < K; ++t) su += u[t];
+#pragma unroll
+  for (int t = 0; t < K; ++t) w[t] = u[t] / su;
+}
+
+template <int E, int Q, int MODE, bool DUMP>
+__device__ __forceinline__ void crossmap_item(
+    const Realization& R, int tile, const float* __restrict__ emb_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
+    const double* __restrict__ tgt_pool, Moments* __restrict__ partial,
+    int query_set, int window, const Dump& dump, Moments* red) {
+  constexpr int K = E + 1;                          // neighbours (Section 3.2)
+  const int tid = threadIdx.x;
+  const double* __restrict__ tgt = tgt_pool + R.tgt_off;
+  const int64_t off = (int64_t)(E - 1) * R.tau;     // time of embedded point 0
+
+  ScanState<E, Q, MODE> S;
+  scan_library<E, Q, MODE>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
+                           query_set, window, S);
 
   // Simplex projection from the E+1 neighbours, then Pearson moments.
   Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
-    if (qi[m] < 0) continue;
+    if (S.qi[m] < 0) continue;
     float nd[K];
     int32_t nj[K];
-    if (MODE == kExclSelf) {
-      // the query itself is at most one of the KS keys (every slot holds a
-      // real candidate: the library has at least KS points); without it the
-      // first K of the others are the neighbours
-      int pos = KS - 1;
-#pragma unroll
-      for (int s = KS - 1; s >= 0; --s)
-        if (key_j(key[m][s]) == qi[m]) pos = s;
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        const double kk = t < pos ? key[m][t] : key[m][t + 1];
-        nd[t] = key_d2(kk);
-        nj[t] = key_j(kk);
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        nd[t] = key_d2(key[m][t]);
-        nj[t] = key_j(key[m][t]);
-      }
-    }
-    double dist[K], u[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) dist[t] = sqrt((double)nd[t]);
-    if (dist[0] > 0.0) {
-#pragma unroll
-      for (int t = 0; t < K; ++t) u[t] = exp(-dist[t] / dist[0]);
-    } else {
-#pragma unroll
-      for (int t = 0; t < K; ++t) u[t] = dist[t] == 0.0 ? 1.0 : 0.0;
-    }
-    double su = 0.0;
-#pragma unroll
-    for (int t = 0; t < K; ++t) su += u[t];
+    select_neighbors<E, Q, MODE>(S, m, nd, nj);
+    double w[K];
+    simplex_weights<K>(nd, w);
     double pred = 0.0;
 #pragma unroll
-    for (int t = 0; t < K; ++t) pred += (u[t] / su) * tgt[nj[t] + off];
-    mom_add(mo, tgt[qi[m] + off], pred);
+    for (int t = 0; t < K; ++t) pred += w[t] * tgt[nj[t] + off];
+    mom_add(mo, tgt[S.qi[m] + off], pred);
     if (DUMP) {
-      const int64_t row = qi[m];
+      const int64_t row = S.qi[m];
 #pragma unroll
       for (int t = 0; t < K; ++t) {
         dump.nbr[row * K + t] = nj[t];
@@ -513,6 +550,104 @@ __device__ __forceinline__ void crossmap_item(
   }
   if (tid == 0) partial[R.slot_base + tile] = red[0];
   __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// many targets per neighbour search (causal matrix)
+// ---------------------------------------------------------------------------
+//
+// One neighbour search over the manifold of series a serves the prediction of
+// every other series b (the library draw does not depend on the series).
+// Per target, the tile's observed/predicted pairs are reduced as sums of
+// values shifted by the target's first embedded value (n, s_o, s_p, s_oo,
+// s_pp, s_op) plus exact min/max of each side (so constant series give NaN
+// exactly), first over the wavefront by a fixed butterfly, then over the
+// four wavefronts in order.
+
+struct Sums {
+  double v[10];   // n, so, sp, soo, spp, sop, min o, max o, min p, max p
+};
+
+__device__ __forceinline__ void sums_merge(Sums& a, const Sums& b) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) a.v[i] += b.v[i];
+  a.v[6] = fmin(a.v[6], b.v[6]);
+  a.v[7] = fmax(a.v[7], b.v[7]);
+  a.v[8] = fmin(a.v[8], b.v[8]);
+  a.v[9] = fmax(a.v[9], b.v[9]);
+}
+
+template <int E, int Q, int MODE>
+__device__ __forceinline__ void crossmap_multi_item(
+    const Realization& R, int tile, const float* __restrict__ emb_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
+    const double* __restrict__ tgt_pool, int64_t n_series, int m_series, int self,
+    Sums* __restrict__ partial, int query_set, int window, Sums* red) {
+  constexpr int K = E + 1;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t off = (int64_t)(E - 1) * R.tau;
+
+  ScanState<E, Q, MODE> S;
+  scan_library<E, Q, MODE>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
+                           query_set, window, S);
+
+  double w[Q][K];
+  int32_t nj[Q][K];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    float nd[K];
+    select_neighbors<E, Q, MODE>(S, m, nd, nj[m]);
+    simplex_weights<K>(nd, w[m]);
+  }
+
+  for (int bt = 0; bt < m_series; ++bt) {
+    if (bt == self) continue;
+    const double* __restrict__ T = tgt_pool + (int64_t)bt * n_series + off;
+    const double shift = T[0];
+    Sums su;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) su.v[i] = 0.0;
+    su.v[6] = su.v[8] = __builtin_inf();
+    su.v[7] = su.v[9] = -__builtin_inf();
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      if (S.qi[m] < 0) continue;
+      double pred = 0.0;
+#pragma unroll
+      for (int t = 0; t < K; ++t) pred += w[m][t] * T[nj[m][t]];
+      const double o = T[S.qi[m]];
+      const double a = o - shift, p = pred - shift;
+      su.v[0] += 1.0;
+      su.v[1] += a;
+      su.v[2] += p;
+      su.v[3] += a * a;
+      su.v[4] += p * p;
+      su.v[5] += a * p;
+      su.v[6] = fmin(su.v[6], o);
+      su.v[7] = fmax(su.v[7], o);
+      su.v[8] = fmin(su.v[8], pred);
+      su.v[9] = fmax(su.v[9], pred);
+    }
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+      Sums o;
+#pragma unroll
+      for (int i = 0; i < 10; ++i) o.v[i] = __shfl_xor(su.v[i], sh, 64);
+      sums_merge(su, o);
+    }
+    if (lane == 0) red[wave] = su;
+    __syncthreads();
+    if (tid == 0) {
+      Sums tot = red[0];
+#pragma unroll
+      for (int wv = 1; wv < kBlock / 64; ++wv) sums_merge(tot, red[wv]);
+      partial[(R.slot_base + tile) * m_series + bt] = tot;
+    }
+    __syncthreads();
+  }
 }
 
 // Work items are taken in list order (the host lists them longest first).
@@ -545,6 +680,65 @@ __global__ __launch_bounds__(kBlock) void k_crossmap(
       __syncthreads();
     }
   }
+}
+
+// Causal-matrix form: realization rz searches the manifold of series
+// R.emb_off's owner (index self_of[rz]) and predicts all m_series series.
+template <int E, int Q, int MODE>
+__global__ __launch_bounds__(kBlock) void k_crossmap_multi(
+    const Realization* __restrict__ rzs, const int32_t* __restrict__ self_of,
+    const Item* __restrict__ items, int n_items, int* __restrict__ next,
+    const float* __restrict__ emb_pool, const float* __restrict__ pts_pool,
+    const int32_t* __restrict__ pj_pool, const int32_t* __restrict__ qord_pool,
+    const int32_t* __restrict__ start_pool, const double* __restrict__ tgt_pool,
+    int64_t n_series, int m_series, Sums* __restrict__ partial, int query_set,
+    int window) {
+  __shared__ Sums red[kBlock / 64];
+  __shared__ int s_next;
+  int it = blockIdx.x;
+  while (it < n_items) {
+    const Item I = items[it];
+    const Realization R = rzs[I.rz];
+    crossmap_multi_item<E, Q, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool,
+                                    start_pool, tgt_pool, n_series, m_series,
+                                    self_of[I.rz], partial, query_set, window, red);
+    if (next == nullptr) {
+      it += gridDim.x;
+    } else {
+      if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(next, 1);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(s_next);
+      __syncthreads();
+    }
+  }
+}
+
+// rho[self][b] of every realization from the per-tile sums; NaN on the
+// diagonal and when either side is constant.
+__global__ void k_finalize_multi(const Realization* __restrict__ rzs,
+                                 const int32_t* __restrict__ self_of, int64_t n_rz,
+                                 int m_series, const Sums* __restrict__ partial,
+                                 int64_t out_stride_b, double* __restrict__ out) {
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x >= n_rz * m_series) return;
+  const int64_t r = x / m_series;
+  const int bt = (int)(x - r * m_series);
+  const Realization R = rzs[r];
+  double rho = __builtin_nan("");
+  if (bt != self_of[r]) {
+    Sums a;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a.v[i] = 0.0;
+    a.v[6] = a.v[8] = __builtin_inf();
+    a.v[7] = a.v[9] = -__builtin_inf();
+    for (int t = 0; t < R.n_tiles; ++t) sums_merge(a, partial[(R.slot_base + t) * m_series + bt]);
+    const double n = a.v[0];
+    const double vo = n * a.v[3] - a.v[1] * a.v[1];
+    const double vp = n * a.v[4] - a.v[2] * a.v[2];
+    const double cv = n * a.v[5] - a.v[1] * a.v[2];
+    if (a.v[6] < a.v[7] && a.v[8] < a.v[9] && vo > 0.0 && vp > 0.0) rho = cv / sqrt(vo * vp);
+  }
+  out[R.out_index + bt * out_stride_b] = rho;
 }
 
 __global__ void k_zero_int(int* p, int n) {
@@ -712,6 +906,67 @@ hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
                      query_set, window, d);
   return hipGetLastError();
 }
+
+template <int E>
+static hipError_t launch_multi_e(int mode, int grid, const Realization* rzs,
+                                 const int32_t* self_of, const Item* items, int n_items,
+                                 int* next, const float* emb, const float* pts,
+                                 const int32_t* pj, const int32_t* qord, const int32_t* start,
+                                 const double* tgt, int64_t n_series, int m_series,
+                                 Sums* partial, int query_set, int window, hipStream_t st) {
+  constexpr int Q = DefaultQ<E>::Q;
+  switch (mode) {
+    case kExclSelf:
+      k_crossmap_multi<E, Q, kExclSelf><<<grid, kBlock, 0, st>>>(
+          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tgt, n_series,
+          m_series, partial, query_set, window);
+      break;
+    case kKeepSelf:
+      k_crossmap_multi<E, Q, kKeepSelf><<<grid, kBlock, 0, st>>>(
+          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tgt, n_series,
+          m_series, partial, query_set, window);
+      break;
+    default:
+      k_crossmap_multi<E, Q, kWindow><<<grid, kBlock, 0, st>>>(
+          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tgt, n_series,
+          m_series, partial, query_set, window);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_crossmap_multi(int E, int mode, int grid, const Realization* rzs,
+                                 const int32_t* self_of, const Item* items, int n_items,
+                                 int* next, const float* emb, const float* pts,
+                                 const int32_t* pj, const int32_t* qord, const int32_t* start,
+                                 const double* tgt, int64_t n_series, int m_series,
+                                 void* partial, int query_set, int window, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  Sums* ps = static_cast<Sums*>(partial);
+  switch (E) {
+#define CCM_MCASE(e)                                                                     \
+  case e:                                                                                \
+    return launch_multi_e<e>(mode, grid, rzs, self_of, items, n_items, next, emb, pts, pj, \
+                             qord, start, tgt, n_series, m_series, ps, query_set, window, st);
+    CCM_MCASE(1) CCM_MCASE(2) CCM_MCASE(3) CCM_MCASE(4) CCM_MCASE(5)
+    CCM_MCASE(6) CCM_MCASE(7) CCM_MCASE(8) CCM_MCASE(9) CCM_MCASE(10)
+#undef CCM_MCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_finalize_multi(const Realization* rzs, const int32_t* self_of,
+                                 int64_t n_rz, int m_series, const void* partial,
+                                 int64_t out_stride_b, double* out, hipStream_t st) {
+  const int64_t n = n_rz * m_series;
+  if (n <= 0) return hipSuccess;
+  k_finalize_multi<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+      rzs, self_of, n_rz, m_series, static_cast<const Sums*>(partial), out_stride_b, out);
+  return hipGetLastError();
+}
+
+size_t multi_sums_bytes() { return sizeof(Sums); }
 
 hipError_t launch_finalize(const Realization* rzs, int64_t n_rz,
                            const Moments* partial, double* out, hipStream_t st) {

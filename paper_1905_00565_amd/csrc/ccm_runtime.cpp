@@ -85,6 +85,7 @@ void upload(DevBuf& b, const std::vector<T>& v) {
 // ---------------------------------------------------------------------------
 
 struct Spec {
+  int32_t M = 0;      // 0: a pair of series (X, Y); M >= 2: causal matrix of M series
   int64_t N = 0;
   std::vector<int32_t> E, tau;
   std::vector<int64_t> L;
@@ -95,7 +96,7 @@ struct Spec {
   uint32_t flags = 0;
 
   bool operator==(const Spec& o) const {
-    return N == o.N && E == o.E && tau == o.tau && L == o.L && r == o.r &&
+    return M == o.M && N == o.N && E == o.E && tau == o.tau && L == o.L && r == o.r &&
            seed == o.seed && excl == o.excl && query_set == o.query_set &&
            (flags & ~CCM_FLAG_NO_GRAPH) == (o.flags & ~CCM_FLAG_NO_GRAPH);
   }
@@ -131,6 +132,7 @@ struct Plan {
   int64_t n_pj = 0;                   // ordered library indices
   int64_t max_sorted_n_e = 0;
   std::vector<Realization> rz;
+  std::vector<int32_t> self_of;       // matrix: searched series of each realization
   // realization r owns sample job rz_sample[r] and gather job r
   std::vector<int64_t> rz_sample;
   // batched items grouped by E, longest library first within a group
@@ -285,6 +287,127 @@ Plan make_plan(const Spec& s) {
   return p;
 }
 
+// Causal matrix: M series, one (E, tau); libraries per (L, r) shared by every
+// series; one realization per (searched series, L, r) predicting all others.
+Plan make_plan_matrix(const Spec& s) {
+  if (s.M < 2) fail(CCM_E_INVAL, "M must be >= 2");
+  if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
+  if (s.L.empty()) fail(CCM_E_INVAL, "empty L list");
+  if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
+  if (s.query_set != 0 && s.query_set != 1) fail(CCM_E_INVAL, "query_set must be 0 or 1");
+  if ((int64_t)s.M * s.N > (int64_t)INT32_MAX / 2) fail(CCM_E_INVAL, "M*N too large");
+  const int32_t E = s.E[0], tau = s.tau[0];
+  if (E < 1 || E > kMaxE) fail(CCM_E_INVAL, "E must be in [1, 10]");
+  if (tau < 1) fail(CCM_E_INVAL, "tau must be >= 1");
+  const int64_t N = s.N;
+  const int64_t ne = N - (int64_t)(E - 1) * tau;
+  if (ne < E + 2) fail(CCM_E_INVAL, "N_e = N - (E-1) tau must be >= E + 2");
+  for (int64_t l : s.L) {
+    if (l < E + 2) fail(CCM_E_INVAL, "every L must be >= E + 2");
+    if (std::min(l, ne) < min_library(E, s.excl))
+      fail(CCM_E_INVAL, "library too small for the exclusion window");
+  }
+  Plan p;
+  p.spec = s;
+  p.mode = excl_mode(s.excl);
+  p.window = s.excl > 0 ? s.excl : 0;
+  const int M = s.M, nL = (int)s.L.size();
+  p.n64 = (int64_t)M * N;
+  p.n32 = (int64_t)M * N;
+  p.ingest.push_back({0, 0, (int64_t)M * N});
+  p.n_series = M;
+  for (int a = 0; a <= M; ++a) p.seg_off.push_back((int32_t)(a * N));
+  p.n_out = (int64_t)M * M * nL * s.r;
+  p.L_eff.assign(nL, 0);
+  const int Q = crossmap_queries_per_lane(E, false);
+  const int64_t qt = (int64_t)kBlock * Q;
+  const int32_t sorted = ne <= gather_max_sorted_n_e() ? 1 : 0;
+  if (sorted) p.max_sorted_n_e = ne;
+  std::vector<int64_t> emb_off(M), qord_off(M);
+  for (int a = 0; a < M; ++a) {
+    emb_off[a] = p.n_emb;
+    qord_off[a] = p.n_qord;
+    p.embed.push_back({a * N, p.n_emb, a * N, p.n_qord, ne, N, E, tau});
+    p.n_emb += ne * E;
+    p.n_qord += ne;
+    p.max_embed = std::max(p.max_embed, ne * E);
+  }
+  std::vector<int64_t> lib_off((size_t)nL * s.r);
+  for (int il = 0; il < nL; ++il) {
+    const int64_t le = std::min(s.L[il], ne);
+    p.L_eff[il] = le;
+    for (int ri = 0; ri < s.r; ++ri) {
+      lib_off[(size_t)il * s.r + ri] = p.n_lib;
+      p.sample.push_back({s.seed, ne, le, p.n_lib, E, tau, ri, 0});
+      p.n_lib += le;
+    }
+  }
+  for (int a = 0; a < M; ++a)
+    for (int il = 0; il < nL; ++il)
+      for (int ri = 0; ri < s.r; ++ri) {
+        const int64_t le = p.L_eff[il];
+        Realization R{};
+        R.emb_off = emb_off[a];
+        R.pts_off = p.n_pts;
+        R.pj_off = p.n_pj;
+        R.qord_off = qord_off[a];
+        R.tgt_off = 0;
+        R.E = E;
+        R.tau = tau;
+        R.n_e = (int32_t)ne;
+        R.l_eff = (int32_t)le;
+        R.n_query = (int32_t)(s.query_set ? le : ne);
+        R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
+        R.slot_base = p.n_slots;
+        R.out_index = (((int64_t)a * M) * nL + il) * s.r + ri;   // target 0 of row a
+        GatherJob gj{};
+        gj.emb_off = R.emb_off;
+        gj.lib_off = lib_off[(size_t)il * s.r + ri];
+        gj.order_off = a * N;
+        gj.pts_off = R.pts_off;
+        gj.pj_off = R.pj_off;
+        gj.start_off = R.slot_base;
+        gj.l_eff = le;
+        gj.n_e = ne;
+        gj.n_series = N;
+        gj.E = E;
+        gj.tau = tau;
+        gj.qt = (int32_t)qt;
+        gj.query_set = s.query_set;
+        gj.sorted = sorted;
+        p.gather.push_back(gj);
+        p.n_pts += le * E;
+        p.n_pj += le;
+        p.n_slots += R.n_tiles;
+        p.rz.push_back(R);
+        p.self_of.push_back(a);
+        p.rz_sample.push_back((int64_t)il * s.r + ri);
+        const double nq = (double)R.n_query;
+        double pairs = nq * (double)le;
+        if (p.mode == kExclSelf) pairs -= s.query_set ? nq : (double)le;
+        p.pairs += pairs;
+        p.flops += pairs * (3.0 * E - 1.0);
+        p.preds += nq * (M - 1);
+      }
+  std::vector<int32_t> order(p.rz.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return p.rz[x].l_eff > p.rz[y].l_eff; });
+  p.e_first[E] = 0;
+  for (int32_t idx : order)
+    for (int t = 0; t < p.rz[idx].n_tiles; ++t) p.items.push_back({idx, t});
+  p.e_count[E] = (int)p.items.size();
+  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
+  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
+                     p.n_series, nullptr, nullptr));
+  p.device_bytes = p.n64 * 8 + p.n32 * 16 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
+                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 + p.sort_temp +
+                   p.n_slots * M * multi_sums_bytes() + p.n_out * 8 +
+                   p.rz.size() * (sizeof(Realization) + 4) + p.items.size() * sizeof(Item) +
+                   p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
+  return p;
+}
+
 // ---------------------------------------------------------------------------
 // execution state of one plan
 // ---------------------------------------------------------------------------
@@ -297,7 +420,7 @@ struct Exec {
   Plan plan;
   DevBuf d_ingest, d_embed, d_sample, d_gather, d_rz, d_items, d_plain_items;
   DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_pj, d_partial, d_out, d_counter;
-  DevBuf d_iota, d_keys_out, d_order, d_segoff, d_sort_temp, d_qord, d_start;
+  DevBuf d_iota, d_keys_out, d_order, d_segoff, d_sort_temp, d_qord, d_start, d_self;
   std::vector<int64_t> plain_first;   // per realization: first plain item
   hipGraphExec_t graph = nullptr;
   ~Exec() {
@@ -358,7 +481,7 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
     c->exec.reset();   // free the previous plan's memory first
   }
   auto ex = std::make_unique<Exec>();
-  ex->plan = make_plan(s);
+  ex->plan = s.M > 0 ? make_plan_matrix(s) : make_plan(s);
   Plan& p = ex->plan;
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
@@ -393,7 +516,12 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
   ex->d_lib.ensure(p.n_lib * 4);
   ex->d_pts.ensure(p.n_pts * 4);
   ex->d_pj.ensure(p.n_pj * 4);
-  ex->d_partial.ensure(p.n_slots * sizeof(Moments));
+  if (s.M > 0) {
+    upload(ex->d_self, p.self_of);
+    ex->d_partial.ensure((size_t)p.n_slots * s.M * multi_sums_bytes());
+  } else {
+    ex->d_partial.ensure(p.n_slots * sizeof(Moments));
+  }
   ex->d_out.ensure(p.n_out * 8);
   ex->d_counter.ensure(64 * sizeof(int));
   c->exec = std::move(ex);
@@ -447,13 +575,23 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
         ev = take_events(c);
         HIPCHK(hipEventRecord(ev.a, st));
       }
-      HIPCHK(launch_crossmap(E, p.mode, false, grid, ex->d_rz.as<Realization>(),
-                             ex->d_items.as<Item>() + p.e_first[E], n, next,
-                             ex->d_emb.as<float>(), ex->d_pts.as<float>(),
-                             ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
-                             ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
-                             ex->d_partial.as<Moments>(), p.spec.query_set, p.window,
-                             nodump, st));
+      if (p.spec.M > 0)
+        HIPCHK(launch_crossmap_multi(E, p.mode, grid, ex->d_rz.as<Realization>(),
+                                     ex->d_self.as<int32_t>(),
+                                     ex->d_items.as<Item>() + p.e_first[E], n, next,
+                                     ex->d_emb.as<float>(), ex->d_pts.as<float>(),
+                                     ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
+                                     ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
+                                     p.spec.N, p.spec.M, ex->d_partial.p, p.spec.query_set,
+                                     p.window, st));
+      else
+        HIPCHK(launch_crossmap(E, p.mode, false, grid, ex->d_rz.as<Realization>(),
+                               ex->d_items.as<Item>() + p.e_first[E], n, next,
+                               ex->d_emb.as<float>(), ex->d_pts.as<float>(),
+                               ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
+                               ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
+                               ex->d_partial.as<Moments>(), p.spec.query_set, p.window,
+                               nodump, st));
       if (timed) {
         HIPCHK(hipEventRecord(ev.b, st));
         c->ev_pending.push_back(ev);
@@ -462,11 +600,14 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
   } else {
     // the unbatched baseline: sampler, gather and cross-map launched per
     // realization
+    std::vector<char> sampled(p.sample.size(), 0);
     for (size_t r = 0; r < p.rz.size(); ++r) {
       const Realization& R = p.rz[r];
       const int64_t sj = p.rz_sample[r];
-      if (r == 0 || p.rz_sample[r - 1] != sj)
+      if (!sampled[sj]) {
         HIPCHK(launch_sample(ex->d_sample.as<SampleJob>() + sj, 1, ex->d_lib.as<int32_t>(), st));
+        sampled[sj] = 1;
+      }
       HIPCHK(launch_gather(ex->d_gather.as<GatherJob>() + r, 1,
                            p.gather[r].sorted ? p.gather[r].n_e : 0, ex->d_emb.as<float>(),
                            ex->d_lib.as<int32_t>(), ex->d_order.as<int32_t>(),
@@ -477,21 +618,37 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
         ev = take_events(c);
         HIPCHK(hipEventRecord(ev.a, st));
       }
-      HIPCHK(launch_crossmap(R.E, p.mode, false, R.n_tiles, ex->d_rz.as<Realization>(),
-                             ex->d_plain_items.as<Item>() + ex->plain_first[r],
-                             R.n_tiles, nullptr, ex->d_emb.as<float>(),
-                             ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
-                             ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
-                             ex->d_s64.as<double>(), ex->d_partial.as<Moments>(),
-                             p.spec.query_set, p.window, nodump, st));
+      if (p.spec.M > 0)
+        HIPCHK(launch_crossmap_multi(R.E, p.mode, R.n_tiles, ex->d_rz.as<Realization>(),
+                                     ex->d_self.as<int32_t>(),
+                                     ex->d_plain_items.as<Item>() + ex->plain_first[r],
+                                     R.n_tiles, nullptr, ex->d_emb.as<float>(),
+                                     ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
+                                     ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
+                                     ex->d_s64.as<double>(), p.spec.N, p.spec.M,
+                                     ex->d_partial.p, p.spec.query_set, p.window, st));
+      else
+        HIPCHK(launch_crossmap(R.E, p.mode, false, R.n_tiles, ex->d_rz.as<Realization>(),
+                               ex->d_plain_items.as<Item>() + ex->plain_first[r],
+                               R.n_tiles, nullptr, ex->d_emb.as<float>(),
+                               ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
+                               ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
+                               ex->d_s64.as<double>(), ex->d_partial.as<Moments>(),
+                               p.spec.query_set, p.window, nodump, st));
       if (timed) {
         HIPCHK(hipEventRecord(ev.b, st));
         c->ev_pending.push_back(ev);
       }
     }
   }
-  HIPCHK(launch_finalize(ex->d_rz.as<Realization>(), (int64_t)p.rz.size(),
-                         ex->d_partial.as<Moments>(), ex->d_out.as<double>(), st));
+  if (p.spec.M > 0)
+    HIPCHK(launch_finalize_multi(ex->d_rz.as<Realization>(), ex->d_self.as<int32_t>(),
+                                 (int64_t)p.rz.size(), p.spec.M, ex->d_partial.p,
+                                 (int64_t)p.spec.L.size() * p.spec.r, ex->d_out.as<double>(),
+                                 st));
+  else
+    HIPCHK(launch_finalize(ex->d_rz.as<Realization>(), (int64_t)p.rz.size(),
+                           ex->d_partial.as<Moments>(), ex->d_out.as<double>(), st));
 }
 
 // Run a prepared plan on stream st: series already in ex->d_s64.
@@ -579,6 +736,14 @@ ccm_status guarded(ccm_ctx* c, F&& f) {
 }
 
 }  // namespace
+
+static Spec make_matrix_spec(int32_t M, int64_t N, int32_t E, int32_t tau, const int64_t* L,
+                             int32_t nL, int32_t r, uint64_t seed, const ccm_opts* opts) {
+  if (M < 2) fail(CCM_E_INVAL, "M must be >= 2");
+  Spec s = make_spec(N, &E, 1, &tau, 1, L, nL, r, seed, opts);
+  s.M = M;
+  return s;
+}
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -701,6 +866,35 @@ ccm_status ccm_dev(ccm_ctx* c, const double* X, const double* Y, int64_t N, int3
                           hipMemcpyDeviceToDevice, st));
     if (L_eff)
       for (int i = 0; i < nL; ++i) L_eff[i] = ex->plan.L_eff[i];
+  });
+}
+
+ccm_status ccm_matrix(ccm_ctx* c, const double* S, int32_t M, int64_t N, int32_t E,
+                      int32_t tau, const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
+                      const ccm_opts* opts, double* rho) {
+  return guarded(c, [&] {
+    if (!rho) fail(CCM_E_INVAL, "rho is NULL");
+    Spec s = make_matrix_spec(M, N, E, tau, L, nL, r, seed, opts);
+    check_host_series(S, (int64_t)M * N, "S");
+    Exec* ex = prepare(c, s);
+    HIPCHK(hipMemcpyAsync(ex->d_s64.p, S, (size_t)M * N * 8, hipMemcpyHostToDevice, c->stream));
+    run(c, ex, c->stream);
+    HIPCHK(hipMemcpyAsync(rho, ex->d_out.p, ex->plan.n_out * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+ccm_status ccm_matrix_dev(ccm_ctx* c, const double* S, int32_t M, int64_t N, int32_t E,
+                          int32_t tau, const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
+                          const ccm_opts* opts, double* rho, void* stream) {
+  return guarded(c, [&] {
+    if (!S || !rho) fail(CCM_E_INVAL, "NULL device pointer");
+    Spec s = make_matrix_spec(M, N, E, tau, L, nL, r, seed, opts);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Exec* ex = prepare(c, s);
+    HIPCHK(hipMemcpyAsync(ex->d_s64.p, S, (size_t)M * N * 8, hipMemcpyDeviceToDevice, st));
+    run(c, ex, st);
+    HIPCHK(hipMemcpyAsync(rho, ex->d_out.p, ex->plan.n_out * 8, hipMemcpyDeviceToDevice, st));
   });
 }
 

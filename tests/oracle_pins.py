@@ -189,6 +189,19 @@ def pin_query_set_library(orc):
     assert np.array_equal(nbr, bn) and np.array_equal(d2, bd)
 
 
+def pin_neighbors_at_matches_full(orc):
+    """Per-query results at listed queries equal the full realization's rows."""
+    rng = np.random.default_rng(15)
+    S = rng.random(120)
+    T = rng.random(120)
+    lib = np.sort(rng.choice(118, size=40, replace=False))
+    nbr, d2, pred, _ = orc.neighbors(S, T, 3, 1, lib)
+    q = np.array([0, 5, 77, 117])
+    n2, d22, p2 = orc.neighbors_at(S, T, 3, 1, lib, q)
+    assert np.array_equal(n2, nbr[q]) and np.array_equal(d22, d2[q])
+    assert np.array_equal(p2, pred[q])
+
+
 def pin_pearson_numpy(orc):
     """Pearson correlation equals numpy.corrcoef (and scipy.stats.pearsonr)."""
     rng = np.random.default_rng(14)
@@ -315,6 +328,7 @@ ALL_PINS = [
     pin_e1_stable_argsort,
     pin_exact_fma_bruteforce,
     pin_query_set_library,
+    pin_neighbors_at_matches_full,
     pin_pearson_numpy,
     pin_self_map_rho_one,
     pin_zero_distance_weights,

@@ -1,0 +1,182 @@
+"""GPU path at the workloads' full sizes, checked on sampled outputs the
+oracle can compute one at a time, and the causal-matrix form.
+
+Bar: rho and predictions within 1e-5 of the oracle, neighbour indices and
+squared distances bit-exact; properties that hold at any size (full-library
+realizations identical across r, forms bitwise equal) where the oracle
+cannot afford the whole output.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_00565_amd import capi, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = capi.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    oracle.build(force=False)
+    return oracle.default()
+
+
+def close(a, b, tol=TOL):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    m = ~np.isnan(a)
+    if m.any():
+        err = np.max(np.abs(a[m] - b[m]))
+        assert err < tol, err
+
+
+# ---------------------------------------------------------------------------
+# causal matrix
+# ---------------------------------------------------------------------------
+
+def small_network(m=5, n=300):
+    s, _ = synth.logistic_network(m, n, seed=17, density=0.3)
+    return s
+
+
+def test_matrix_small_vs_oracle(ctx, orc):
+    S = small_network()
+    M = S.shape[0]
+    L = [20, 100, 298]
+    r = 3
+    rho = ctx.ccm_matrix(S, 3, 1, L, r, 21)
+    assert rho.shape == (M, M, len(L), r)
+    tasks, where = [], []
+    for a in range(M):
+        for b in range(M):
+            if a == b:
+                assert np.isnan(rho[a, a]).all()
+                continue
+            for il, l in enumerate(L):
+                for ri in range(r):
+                    tasks.append((S[a], S[b], 3, 1, l, ri, 21, 0, 0))
+                    where.append((a, b, il, ri))
+    want = orc.realizations_threaded(tasks)
+    got = [rho[w] for w in where]
+    close(got, want)
+
+
+def test_matrix_equals_pairwise_ccm(ctx):
+    S = small_network()
+    L = [30, 200]
+    rho = ctx.ccm_matrix(S, 2, 2, L, 4, 8)
+    for a, b in [(0, 1), (3, 2), (4, 0)]:
+        rxy, _, _ = ctx.ccm(S[b], S[a], 2, 2, L, 4, 8)   # X = S[b] from M_Y, Y = S[a]
+        assert np.max(np.abs(rho[a, b] - rxy)) < 1e-12
+
+
+def test_matrix_forms_and_device(ctx):
+    import torch
+    S = small_network(4, 260)
+    args = (S, 4, 1, [25, 260], 3, 5)
+    ref = ctx.ccm_matrix(*args)
+    for flags in (capi.CCM_FLAG_PLAIN, capi.CCM_FLAG_NO_GRAPH, capi.CCM_FLAG_PERSISTENT):
+        assert np.array_equal(ctx.ccm_matrix(*args, flags=flags), ref, equal_nan=True), flags
+    dS = torch.tensor(S, device="cuda:0")
+    out = torch.empty(ref.shape, dtype=torch.float64, device="cuda:0")
+    ctx.ccm_matrix_dev(dS, 4, 1, [25, 260], 3, 5, out, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref, equal_nan=True)
+
+
+def test_matrix_options(ctx, orc):
+    S = small_network(3, 200)
+    rho = ctx.ccm_matrix(S, 2, 1, [40], 2, 3, exclusion_radius=-1)
+    want = orc.realization(S[0], S[2], 2, 1, 40, 1, 3, excl=-1)[0]
+    assert abs(rho[0, 2, 0, 1] - want) < TOL
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads
+# ---------------------------------------------------------------------------
+
+def test_sweep_full_size_sampled(ctx, orc):
+    """The parameter sweep the bench times: N=10^4, E=1..10, tau=1..5, 20 L,
+    r=250, in the bench's launch configuration (batched, graph)."""
+    w = synth.workload_sweep()
+    rho = ctx.ccm_sweep(w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed)
+    assert np.isfinite(rho).all()
+    rng = np.random.default_rng(99)
+    picks = []
+    for k in range(28):
+        ie = k % 10
+        it = int(rng.integers(5))
+        # mostly small and middle libraries, a few of the largest
+        il = int(rng.integers(20)) if k % 7 == 0 else int(rng.integers(12))
+        ri = int(rng.integers(w.r))
+        d = k % 2
+        picks.append((d, ie, it, il, ri))
+    tasks = []
+    for d, ie, it, il, ri in picks:
+        S, T = (w.Y, w.X) if d == 0 else (w.X, w.Y)
+        tasks.append((S, T, w.E[ie], w.tau[it], w.L[il], ri, w.seed, 0, 0))
+    want = orc.realizations_threaded(tasks)
+    got = [rho[p] for p in picks]
+    close(got, want)
+    # L = 10^4 clamps to N_e: all r realizations are the same library
+    full = rho[:, :, :, -1, :]
+    assert np.array_equal(full, np.repeat(full[..., :1], w.r, axis=-1))
+
+
+def test_long_series_sampled(ctx, orc):
+    """Noisy coupled logistic map N=10^5, E=3, tau=2, L up to 10^5, r=250."""
+    w = synth.workload_long()
+    rxy, ryx, le = ctx.ccm(w.X, w.Y, 3, 2, w.L, w.r, w.seed)
+    assert le.tolist() == [1000, 10000, 50000, 99996]
+    assert np.isfinite(rxy).all() and np.isfinite(ryx).all()
+    tasks = [(w.Y, w.X, 3, 2, 1000, ri, w.seed, 0, 0) for ri in (0, 7, 249)]
+    tasks += [(w.X, w.Y, 3, 2, 1000, 3, w.seed, 0, 0),
+              (w.Y, w.X, 3, 2, 10000, 11, w.seed, 0, 0)]
+    want = orc.realizations_threaded(tasks)
+    close([rxy[0, 0], rxy[0, 7], rxy[0, 249], ryx[0, 3], rxy[1, 11]], want)
+    # full library: every r identical, and equal to the per-query hook's rho
+    assert np.all(rxy[3] == rxy[3, 0]) and np.all(ryx[3] == ryx[3, 0])
+    ne = 99996
+    lib = np.arange(ne, dtype=np.int32)
+    nbr, d2, pred, rho = ctx.ccm_neighbors(w.Y, w.X, 3, 2, lib)
+    assert abs(rho - rxy[3, 0]) < 1e-12
+    # sampled queries of a library of 5*10^4: bit-exact neighbours, predictions
+    lib5 = ctx.ccm_library(ne, 3, 2, 50000, 5, w.seed)
+    assert np.array_equal(lib5, orc.sample_library(w.seed, 3, 2, 50000, 5, ne))
+    nbr5, d25, pred5, _ = ctx.ccm_neighbors(w.Y, w.X, 3, 2, lib5)
+    q = np.random.default_rng(3).choice(ne, 64, replace=False)
+    on, od, op = orc.neighbors_at(w.Y, w.X, 3, 2, lib5, q)
+    assert np.array_equal(nbr5[q], on) and np.array_equal(d25[q], od)
+    assert np.max(np.abs(pred5[q] - op)) < TOL
+    on, od, op = orc.neighbors_at(w.Y, w.X, 3, 2, lib, q[:16])
+    assert np.array_equal(nbr[q[:16]], on) and np.array_equal(d2[q[:16]], od)
+    assert np.max(np.abs(pred[q[:16]] - op)) < TOL
+
+
+def test_matrix_full_size_sampled(ctx, orc):
+    """64-series logistic network, N=2*10^4, E=4, tau=1, 10 L, r=100."""
+    w = synth.workload_matrix()
+    S = w["S"]
+    M = S.shape[0]
+    rho = ctx.ccm_matrix(S, w["E"], w["tau"], w["L"], w["r"], w["seed"])
+    assert rho.shape == (M, M, 10, w["r"])
+    off = ~np.eye(M, dtype=bool)
+    assert np.isfinite(rho[off]).all() and np.isnan(rho[~off]).all()
+    rng = np.random.default_rng(5)
+    picks, tasks = [], []
+    for k in range(12):
+        a, b = rng.choice(M, 2, replace=False)
+        il = int(rng.integers(3)) if k < 10 else 9
+        ri = int(rng.integers(w["r"]))
+        picks.append((a, b, il, ri))
+        tasks.append((S[a], S[b], w["E"], w["tau"], w["L"][il], ri, w["seed"], 0, 0))
+    want = orc.realizations_threaded(tasks)
+    close([rho[p] for p in picks], want)

@@ -21,7 +21,8 @@ MUTANTS = [
      "Sf[ti - (int64_t)k] - Sf[tj - (int64_t)k]"),
     ("unfused accumulate", "acc = fmaf(diff, diff, acc);", "acc = diff * diff + acc;"),
     ("ties to higher index", "(a.d2 == b.d2 && a.j < b.j)", "(a.d2 == b.d2 && a.j > b.j)"),
-    ("E neighbours instead of E+1", "const int k = E + 1;", "const int k = E;"),
+    ("E neighbours instead of E+1", "const int k = E + 1;\n    int n = 0;",
+     "const int k = E;\n    int n = 0;"),
     ("weights not scaled by d_1", "u[m] = exp(-d[m] / d[0]);", "u[m] = exp(-d[m]);"),
     ("weights from squared distance", "d[m] = sqrt((double)best[m].d2);",
      "d[m] = (double)best[m].d2;"),

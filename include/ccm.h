@@ -172,6 +172,65 @@ ccm_status ccm_matrix_dev(ccm_ctx *ctx, const double *S, int32_t M, int64_t N,
                           double *rho, void *stream);
 
 /*
+ * Served form: continuous batching of independent cross-map jobs (paper
+ * Section 3.3: several (L, tau, E) pipelines run concurrently instead of one
+ * after the other).  Jobs are queued at submit, admitted in arrival order
+ * while their device footprint fits the server's HBM budget (and at most
+ * max_jobs are admitted), and their work is interleaved on the GPU in epochs
+ * of about epoch_target_ms: work of jobs that arrive while others run
+ * overlaps with theirs.  A job's result is the same, bit for bit, whether it
+ * ran alone or in a mix.
+ */
+typedef struct ccm_server ccm_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes;  /* device arena for job data; 0 = default
+                                 (a quarter of free memory, at most 32 GiB) */
+  int32_t max_jobs;           /* admitted at once; <= 0 = 64 */
+  double epoch_target_ms;     /* device time per epoch; <= 0 = 20 ms */
+} ccm_server_cfg;
+
+/* One job: as ccm() (both directions, one E and tau).  Every array is
+   copied at submit; flags in opts are ignored. */
+typedef struct {
+  const double *X, *Y;
+  int64_t N;
+  int32_t E, tau;
+  const int64_t *L;
+  int32_t nL;
+  int32_t r;
+  uint64_t seed;
+  ccm_opts opts;
+} ccm_job;
+
+/* Seconds since the server was created; work counts of the job; the
+   device bytes it held while admitted (its footprint against the budget). */
+typedef struct {
+  double t_submit, t_admit, t_done;
+  uint64_t pairs, predictions, realizations;
+  uint64_t device_bytes;
+} ccm_job_stats;
+
+/* Start a server on the context's device (its own stream and thread). */
+ccm_status ccm_server_create(ccm_ctx *ctx, const ccm_server_cfg *cfg,
+                             ccm_server **out);
+/* Queue a job; never waits for the GPU.  CCM_E_INVAL for a malformed job,
+   CCM_E_NOMEM if its footprint exceeds the whole budget. */
+ccm_status ccm_submit(ccm_server *srv, const ccm_job *job, uint64_t *ticket);
+/* Wait until the job is finished (timeout_ns < 0: no limit).
+   CCM_E_TIMEOUT if it is not finished in time, CCM_E_NOTFOUND for an unknown
+   or cancelled ticket, the job's error status if it failed. */
+ccm_status ccm_wait(ccm_server *srv, uint64_t ticket, int64_t timeout_ns);
+/* Copy a finished job's rho (host double[nL][r] each, nullable) and stats,
+   and release the ticket.  CCM_E_BUSY while the job is still running. */
+ccm_status ccm_result(ccm_server *srv, uint64_t ticket, double *rho_X_from_MY,
+                      double *rho_Y_from_MX, ccm_job_stats *stats);
+/* Cancel a queued or running job (its remaining work is skipped). */
+ccm_status ccm_cancel(ccm_server *srv, uint64_t ticket);
+/* Cancel everything outstanding, wait for the device, release the server. */
+void ccm_server_destroy(ccm_server *srv);
+
+/*
  * Test hook: the library subsample the sampler draws for realization
  * r_index of (E, tau, L_eff) under seed, over N_e embedded points.
  *   idx_out     host int32[L_eff], ascending embedded-point indices

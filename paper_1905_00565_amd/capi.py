@@ -36,6 +36,8 @@ EXPORTS = [
     "ccm_matrix", "ccm_dev", "ccm_sweep_dev", "ccm_matrix_dev", "ccm_library",
     "ccm_neighbors",
     "ccm_profile_enable", "ccm_profile_read",
+    "ccm_server_create", "ccm_submit", "ccm_wait", "ccm_result", "ccm_cancel",
+    "ccm_server_destroy",
 ]
 
 
@@ -48,6 +50,23 @@ class ccm_profile(C.Structure):
     _fields_ = [("kernel_ms", C.c_double), ("launches", C.c_int64),
                 ("pairs", C.c_double), ("flops", C.c_double),
                 ("predictions", C.c_double), ("realizations", C.c_double)]
+
+
+class ccm_server_cfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_jobs", C.c_int32),
+                ("epoch_target_ms", C.c_double)]
+
+
+class ccm_job(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("Y", C.c_void_p), ("N", C.c_int64), ("E", C.c_int32),
+                ("tau", C.c_int32), ("L", C.c_void_p), ("nL", C.c_int32), ("r", C.c_int32),
+                ("seed", C.c_uint64), ("opts", ccm_opts)]
+
+
+class ccm_job_stats(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("pairs", C.c_uint64), ("predictions", C.c_uint64),
+                ("realizations", C.c_uint64), ("device_bytes", C.c_uint64)]
 
 
 class CCMError(RuntimeError):
@@ -87,10 +106,17 @@ def lib():
         L.ccm_matrix_dev.argtypes = [P, P, i32, i64, i32, i32, P, i32, i32, u64, P, P, P]
         L.ccm_library.argtypes = [P, i64, i32, i32, i64, i32, u64, P]
         L.ccm_neighbors.argtypes = [P, P, P, i64, i32, i32, P, i64, P, P, P, P, P]
+        L.ccm_server_create.argtypes = [P, C.POINTER(ccm_server_cfg), C.POINTER(P)]
+        L.ccm_submit.argtypes = [P, C.POINTER(ccm_job), C.POINTER(u64)]
+        L.ccm_wait.argtypes = [P, u64, i64]
+        L.ccm_result.argtypes = [P, u64, P, P, C.POINTER(ccm_job_stats)]
+        L.ccm_cancel.argtypes = [P, u64]
+        L.ccm_server_destroy.argtypes = [P]
+        L.ccm_server_destroy.restype = None
         L.ccm_profile_enable.argtypes = [P, C.c_int]
         L.ccm_profile_read.argtypes = [P, C.POINTER(ccm_profile), C.c_int]
         for name in EXPORTS:
-            if name not in ("ccm_destroy", "ccm_last_error"):
+            if name not in ("ccm_destroy", "ccm_last_error", "ccm_server_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -269,6 +295,81 @@ def ccm_profile_read(ctx, reset=True) -> dict:
     p = ccm_profile()
     _check(ctx, lib().ccm_profile_read(ctx, C.byref(p), 1 if reset else 0))
     return {f: getattr(p, f) for f, _ in ccm_profile._fields_}
+
+
+def ccm_server_create(ctx, hbm_budget_bytes=0, max_jobs=0, epoch_target_ms=0.0):
+    cfg = ccm_server_cfg(int(hbm_budget_bytes), int(max_jobs), float(epoch_target_ms))
+    h = C.c_void_p()
+    _check(ctx, lib().ccm_server_create(ctx, C.byref(cfg), C.byref(h)))
+    return h
+
+
+def ccm_submit(srv, X, Y, E, tau, L, r, seed, exclusion_radius=0, query_set=0, ctx=None):
+    """Queue a job; returns its ticket.  Arrays are copied by the call."""
+    X, Y = _f64(X), _f64(Y)
+    if len(X) != len(Y):
+        raise ValueError("X and Y must have the same length")
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    job = ccm_job(_ptr(X), _ptr(Y), len(X), E, tau, _ptr(Ls), len(Ls), r,
+                  seed & (2**64 - 1), _opts(exclusion_radius, query_set, 0))
+    t = C.c_uint64()
+    _check(ctx, lib().ccm_submit(srv, C.byref(job), C.byref(t)))
+    return t.value
+
+
+def ccm_wait(srv, ticket, timeout_ns=-1) -> int:
+    """Status of the wait (CCM_OK, CCM_E_TIMEOUT, ...); does not raise."""
+    return int(lib().ccm_wait(srv, ticket, timeout_ns))
+
+
+def ccm_result(srv, ticket, nL, r):
+    """(rho_xy [nL][r], rho_yx [nL][r], stats dict); raises on a failed job."""
+    rxy = np.empty((nL, r))
+    ryx = np.empty((nL, r))
+    st = ccm_job_stats()
+    status = lib().ccm_result(srv, ticket, _ptr(rxy), _ptr(ryx), C.byref(st))
+    if status != CCM_OK:
+        raise CCMError(status, f"job {ticket}")
+    return rxy, ryx, {f: getattr(st, f) for f, _ in ccm_job_stats._fields_}
+
+
+def ccm_cancel(srv, ticket) -> int:
+    return int(lib().ccm_cancel(srv, ticket))
+
+
+def ccm_server_destroy(srv) -> None:
+    lib().ccm_server_destroy(srv)
+
+
+class Server:
+    """Owns one server; methods forward to the functions above."""
+
+    def __init__(self, ctx, **cfg):
+        self.ctx = ctx.handle if isinstance(ctx, Context) else ctx
+        self.handle = ccm_server_create(self.ctx, **cfg)
+
+    def submit(self, *a, **k):
+        return ccm_submit(self.handle, *a, ctx=self.ctx, **k)
+
+    def wait(self, ticket, timeout_ns=-1):
+        return ccm_wait(self.handle, ticket, timeout_ns)
+
+    def result(self, ticket, nL, r):
+        return ccm_result(self.handle, ticket, nL, r)
+
+    def cancel(self, ticket):
+        return ccm_cancel(self.handle, ticket)
+
+    def close(self):
+        if self.handle:
+            ccm_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Context:

@@ -1,0 +1,157 @@
+// ccm_host.h -- host-side pieces of libccm shared by the runtime and the
+// server: error handling, device buffers, call specifications and plans.
+// Internal to libccm; the public boundary is include/ccm.h.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ccm.h"
+#include "ccm_internal.h"
+
+namespace ccmh {
+
+using namespace ccmk;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+struct Fail {
+  ccm_status status;
+  std::string what;
+};
+
+[[noreturn]] inline void fail(ccm_status st, const std::string& what) { throw Fail{st, what}; }
+
+inline void hip_check(hipError_t e, const char* expr) {
+  if (e == hipSuccess) return;
+  const ccm_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+                            ? CCM_E_NOMEM
+                            : CCM_E_DEVICE;
+  fail(st, std::string(expr) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr) hip_check((expr), #expr)
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t n) {
+    if (n <= bytes && p) return;
+    release();
+    if (n == 0) n = 256;
+    HIPCHK(hipMalloc(&p, n));
+    bytes = n;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& v) {
+  b.ensure(v.size() * sizeof(T));
+  if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+
+struct Spec {
+  int32_t M = 0;      // 0: a pair of series (X, Y); M >= 2: causal matrix of M series
+  int64_t N = 0;
+  std::vector<int32_t> E, tau;
+  std::vector<int64_t> L;
+  int32_t r = 0;
+  uint64_t seed = 0;
+  int32_t excl = 0;
+  int32_t query_set = 0;
+  uint32_t flags = 0;
+
+  bool operator==(const Spec& o) const {
+    return M == o.M && N == o.N && E == o.E && tau == o.tau && L == o.L && r == o.r &&
+           seed == o.seed && excl == o.excl && query_set == o.query_set &&
+           (flags & ~CCM_FLAG_NO_GRAPH) == (o.flags & ~CCM_FLAG_NO_GRAPH);
+  }
+};
+
+inline int excl_mode(int32_t excl) {
+  if (excl == 0) return kExclSelf;
+  if (excl < 0) return kKeepSelf;
+  return kWindow;
+}
+
+inline int64_t min_library(int32_t E, int32_t excl) {
+  const int64_t w = excl < 0 ? 0 : 2 * (int64_t)excl + 1;
+  return (int64_t)E + 1 + w;
+}
+
+struct Plan {
+  Spec spec;
+  int mode = kExclSelf;
+  int window = 0;
+  std::vector<IngestJob> ingest;
+  int64_t n64 = 0, n32 = 0;
+  std::vector<EmbedJob> embed;
+  int64_t n_emb = 0, max_embed = 0;
+  int64_t n_qord = 0;                 // query-order entries (sum of n_e)
+  int32_t n_series = 2;               // series sorted (segments)
+  std::vector<int32_t> seg_off;       // segment offsets of the value sort
+  size_t sort_temp = 0;
+  std::vector<SampleJob> sample;
+  int64_t n_lib = 0;
+  std::vector<GatherJob> gather;
+  int64_t n_pts = 0;                  // floats of ordered library coordinates
+  int64_t n_pj = 0;                   // ordered library indices
+  int64_t max_sorted_n_e = 0;
+  std::vector<Realization> rz;
+  std::vector<int32_t> self_of;       // matrix: searched series of each realization
+  // realization r owns sample job rz_sample[r] and gather job r
+  std::vector<int64_t> rz_sample;
+  // batched items grouped by E, longest library first within a group
+  std::vector<Item> items;
+  int e_first[kMaxE + 1] = {0};
+  int e_count[kMaxE + 1] = {0};
+  int64_t n_slots = 0;
+  int64_t n_out = 0;
+  std::vector<int64_t> L_eff;   // per (iE, itau, iL)
+  double pairs = 0, flops = 0, preds = 0;
+  size_t device_bytes = 0;
+};
+
+// Validate a sweep (pair of series, E x tau grid) and lay out every
+// realization of it.
+Plan make_plan(const Spec& s);
+// Causal matrix: M series, one (E, tau); libraries per (L, r) shared by every
+// series; one realization per (searched series, L, r) predicting all others.
+Plan make_plan_matrix(const Spec& s);
+
+// Host series: finite and |value| <= 1e17 (keeps binary32 d2 finite).
+void check_host_series(const double* s, int64_t n, const char* name);
+
+// A call's specification from C-ABI arguments (validation happens when the
+// plan is made).
+Spec make_spec(int64_t N, const int32_t* E, int32_t nE, const int32_t* tau, int32_t ntau,
+               const int64_t* L, int32_t nL, int32_t r, uint64_t seed, const ccm_opts* opts);
+
+}  // namespace ccmh

@@ -1,0 +1,297 @@
+// ccm_plan.cpp -- validation of a call and layout of its realizations,
+// work items and device pools (the planner of libccm).
+#include "ccm_host.h"
+
+namespace ccmh {
+
+// Validate a sweep and lay out every realization of it.
+Plan make_plan(const Spec& s) {
+  if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
+  if (s.E.empty() || s.tau.empty() || s.L.empty()) fail(CCM_E_INVAL, "empty E, tau or L list");
+  if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
+  if (s.query_set != 0 && s.query_set != 1) fail(CCM_E_INVAL, "query_set must be 0 or 1");
+  if (s.N > (int64_t)INT32_MAX / 2) fail(CCM_E_INVAL, "N too large");
+  for (int32_t e : s.E)
+    if (e < 1 || e > kMaxE) fail(CCM_E_INVAL, "E must be in [1, 10]");
+  for (int32_t t : s.tau)
+    if (t < 1) fail(CCM_E_INVAL, "tau must be >= 1");
+  for (int32_t e : s.E)
+    for (int32_t t : s.tau) {
+      const int64_t ne = s.N - (int64_t)(e - 1) * t;
+      if (ne < e + 2) fail(CCM_E_INVAL, "N_e = N - (E-1) tau must be >= E + 2");
+      for (int64_t l : s.L) {
+        if (l < e + 2) fail(CCM_E_INVAL, "every L must be >= E + 2");
+        if (std::min(l, ne) < min_library(e, s.excl))
+          fail(CCM_E_INVAL, "library too small for the exclusion window");
+      }
+    }
+
+  Plan p;
+  p.spec = s;
+  p.mode = excl_mode(s.excl);
+  p.window = s.excl > 0 ? s.excl : 0;
+  const int nE = (int)s.E.size(), nT = (int)s.tau.size(), nL = (int)s.L.size();
+  const int64_t N = s.N;
+  p.n64 = 2 * N;
+  p.n32 = 2 * N;
+  p.ingest.push_back({0, 0, 2 * N});
+  p.n_series = 2;
+  p.seg_off = {0, (int32_t)N, (int32_t)(2 * N)};
+  const int64_t sorted_limit = gather_max_sorted_n_e();
+  p.n_out = 2LL * nE * nT * nL * s.r;
+  p.L_eff.assign((size_t)nE * nT * nL, 0);
+
+  for (int ie = 0; ie < nE; ++ie) {
+    const int32_t E = s.E[ie];
+    const int Q = crossmap_queries_per_lane(E, false);
+    const int64_t qt = (int64_t)kBlock * Q;
+    for (int it = 0; it < nT; ++it) {
+      const int32_t tau = s.tau[it];
+      const int64_t ne = N - (int64_t)(E - 1) * tau;
+      int64_t emb_off[2], qord_off[2];
+      for (int sr = 0; sr < 2; ++sr) {
+        emb_off[sr] = p.n_emb;
+        qord_off[sr] = p.n_qord;
+        p.embed.push_back({sr * N, p.n_emb, sr * N, p.n_qord, ne, N, E, tau});
+        p.n_emb += ne * E;
+        p.n_qord += ne;
+        p.max_embed = std::max(p.max_embed, ne * E);
+      }
+      const int32_t sorted = ne <= sorted_limit ? 1 : 0;
+      if (sorted) p.max_sorted_n_e = std::max(p.max_sorted_n_e, ne);
+      for (int il = 0; il < nL; ++il) {
+        const int64_t le = std::min(s.L[il], ne);
+        p.L_eff[((size_t)ie * nT + it) * nL + il] = le;
+        for (int ri = 0; ri < s.r; ++ri) {
+          const int64_t lib_off = p.n_lib;
+          p.sample.push_back({s.seed, ne, le, lib_off, E, tau, ri, 0});
+          p.n_lib += le;
+          for (int dir = 0; dir < 2; ++dir) {
+            // dir 0: library Y (series 1) predicts X (series 0); dir 1: reverse
+            const int lib_s = dir == 0 ? 1 : 0;
+            const int tgt_s = dir == 0 ? 0 : 1;
+            Realization R{};
+            R.emb_off = emb_off[lib_s];
+            R.pts_off = p.n_pts;
+            R.pj_off = p.n_pj;
+            R.qord_off = qord_off[lib_s];
+            R.tgt_off = tgt_s * N;
+            R.E = E;
+            R.tau = tau;
+            R.n_e = (int32_t)ne;
+            R.l_eff = (int32_t)le;
+            R.n_query = (int32_t)(s.query_set ? le : ne);
+            R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
+            R.slot_base = p.n_slots;
+            R.out_index = ((((int64_t)dir * nE + ie) * nT + it) * nL + il) * s.r + ri;
+            GatherJob gj{};
+            gj.emb_off = R.emb_off;
+            gj.lib_off = lib_off;
+            gj.order_off = lib_s * N;
+            gj.pts_off = R.pts_off;
+            gj.pj_off = R.pj_off;
+            gj.start_off = R.slot_base;
+            gj.l_eff = le;
+            gj.n_e = ne;
+            gj.n_series = N;
+            gj.E = E;
+            gj.tau = tau;
+            gj.qt = (int32_t)qt;
+            gj.query_set = s.query_set;
+            gj.sorted = sorted;
+            p.gather.push_back(gj);
+            p.n_pts += le * E;
+            p.n_pj += le;
+            p.n_slots += R.n_tiles;
+            p.rz.push_back(R);
+            p.rz_sample.push_back((int64_t)p.sample.size() - 1);
+            // algorithmic work: every (query, candidate) pair but the query itself
+            const double nq = (double)R.n_query;
+            double pairs = nq * (double)le;
+            if (p.mode == kExclSelf) pairs -= s.query_set ? nq : (double)le;
+            p.pairs += pairs;
+            p.flops += pairs * (3.0 * E - 1.0);
+            p.preds += nq;
+          }
+        }
+      }
+    }
+  }
+  if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
+
+  // Items grouped by E; within a group the longest libraries go first.
+  std::vector<int32_t> order(p.rz.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (p.rz[a].E != p.rz[b].E) return p.rz[a].E < p.rz[b].E;
+    return p.rz[a].l_eff > p.rz[b].l_eff;
+  });
+  for (int32_t idx : order) {
+    const Realization& R = p.rz[idx];
+    if (p.e_count[R.E] == 0) p.e_first[R.E] = (int)p.items.size();
+    for (int t = 0; t < R.n_tiles; ++t) p.items.push_back({idx, t});
+    p.e_count[R.E] += R.n_tiles;
+  }
+  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
+
+  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
+                     p.n_series, nullptr, nullptr));
+  p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
+                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 + p.sort_temp +
+                   (size_t)p.n32 * 12 +
+                   p.n_slots * sizeof(Moments) + p.n_out * 8 +
+                   p.rz.size() * sizeof(Realization) + p.items.size() * sizeof(Item) +
+                   p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
+  return p;
+}
+
+// Causal matrix: M series, one (E, tau); libraries per (L, r) shared by every
+// series; one realization per (searched series, L, r) predicting all others.
+Plan make_plan_matrix(const Spec& s) {
+  if (s.M < 2) fail(CCM_E_INVAL, "M must be >= 2");
+  if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
+  if (s.L.empty()) fail(CCM_E_INVAL, "empty L list");
+  if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
+  if (s.query_set != 0 && s.query_set != 1) fail(CCM_E_INVAL, "query_set must be 0 or 1");
+  if ((int64_t)s.M * s.N > (int64_t)INT32_MAX / 2) fail(CCM_E_INVAL, "M*N too large");
+  const int32_t E = s.E[0], tau = s.tau[0];
+  if (E < 1 || E > kMaxE) fail(CCM_E_INVAL, "E must be in [1, 10]");
+  if (tau < 1) fail(CCM_E_INVAL, "tau must be >= 1");
+  const int64_t N = s.N;
+  const int64_t ne = N - (int64_t)(E - 1) * tau;
+  if (ne < E + 2) fail(CCM_E_INVAL, "N_e = N - (E-1) tau must be >= E + 2");
+  for (int64_t l : s.L) {
+    if (l < E + 2) fail(CCM_E_INVAL, "every L must be >= E + 2");
+    if (std::min(l, ne) < min_library(E, s.excl))
+      fail(CCM_E_INVAL, "library too small for the exclusion window");
+  }
+  Plan p;
+  p.spec = s;
+  p.mode = excl_mode(s.excl);
+  p.window = s.excl > 0 ? s.excl : 0;
+  const int M = s.M, nL = (int)s.L.size();
+  p.n64 = (int64_t)M * N;
+  p.n32 = (int64_t)M * N;
+  p.ingest.push_back({0, 0, (int64_t)M * N});
+  p.n_series = M;
+  for (int a = 0; a <= M; ++a) p.seg_off.push_back((int32_t)(a * N));
+  p.n_out = (int64_t)M * M * nL * s.r;
+  p.L_eff.assign(nL, 0);
+  const int Q = crossmap_queries_per_lane(E, false);
+  const int64_t qt = (int64_t)kBlock * Q;
+  const int32_t sorted = ne <= gather_max_sorted_n_e() ? 1 : 0;
+  if (sorted) p.max_sorted_n_e = ne;
+  std::vector<int64_t> emb_off(M), qord_off(M);
+  for (int a = 0; a < M; ++a) {
+    emb_off[a] = p.n_emb;
+    qord_off[a] = p.n_qord;
+    p.embed.push_back({a * N, p.n_emb, a * N, p.n_qord, ne, N, E, tau});
+    p.n_emb += ne * E;
+    p.n_qord += ne;
+    p.max_embed = std::max(p.max_embed, ne * E);
+  }
+  std::vector<int64_t> lib_off((size_t)nL * s.r);
+  for (int il = 0; il < nL; ++il) {
+    const int64_t le = std::min(s.L[il], ne);
+    p.L_eff[il] = le;
+    for (int ri = 0; ri < s.r; ++ri) {
+      lib_off[(size_t)il * s.r + ri] = p.n_lib;
+      p.sample.push_back({s.seed, ne, le, p.n_lib, E, tau, ri, 0});
+      p.n_lib += le;
+    }
+  }
+  for (int a = 0; a < M; ++a)
+    for (int il = 0; il < nL; ++il)
+      for (int ri = 0; ri < s.r; ++ri) {
+        const int64_t le = p.L_eff[il];
+        Realization R{};
+        R.emb_off = emb_off[a];
+        R.pts_off = p.n_pts;
+        R.pj_off = p.n_pj;
+        R.qord_off = qord_off[a];
+        R.tgt_off = 0;
+        R.E = E;
+        R.tau = tau;
+        R.n_e = (int32_t)ne;
+        R.l_eff = (int32_t)le;
+        R.n_query = (int32_t)(s.query_set ? le : ne);
+        R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
+        R.slot_base = p.n_slots;
+        R.out_index = (((int64_t)a * M) * nL + il) * s.r + ri;   // target 0 of row a
+        GatherJob gj{};
+        gj.emb_off = R.emb_off;
+        gj.lib_off = lib_off[(size_t)il * s.r + ri];
+        gj.order_off = a * N;
+        gj.pts_off = R.pts_off;
+        gj.pj_off = R.pj_off;
+        gj.start_off = R.slot_base;
+        gj.l_eff = le;
+        gj.n_e = ne;
+        gj.n_series = N;
+        gj.E = E;
+        gj.tau = tau;
+        gj.qt = (int32_t)qt;
+        gj.query_set = s.query_set;
+        gj.sorted = sorted;
+        p.gather.push_back(gj);
+        p.n_pts += le * E;
+        p.n_pj += le;
+        p.n_slots += R.n_tiles;
+        p.rz.push_back(R);
+        p.self_of.push_back(a);
+        p.rz_sample.push_back((int64_t)il * s.r + ri);
+        const double nq = (double)R.n_query;
+        double pairs = nq * (double)le;
+        if (p.mode == kExclSelf) pairs -= s.query_set ? nq : (double)le;
+        p.pairs += pairs;
+        p.flops += pairs * (3.0 * E - 1.0);
+        p.preds += nq * (M - 1);
+      }
+  std::vector<int32_t> order(p.rz.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return p.rz[x].l_eff > p.rz[y].l_eff; });
+  p.e_first[E] = 0;
+  for (int32_t idx : order)
+    for (int t = 0; t < p.rz[idx].n_tiles; ++t) p.items.push_back({idx, t});
+  p.e_count[E] = (int)p.items.size();
+  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
+  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
+                     p.n_series, nullptr, nullptr));
+  p.device_bytes = p.n64 * 8 + p.n32 * 16 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
+                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 + p.sort_temp +
+                   p.n_slots * M * multi_sums_bytes() + p.n_out * 8 +
+                   p.rz.size() * (sizeof(Realization) + 4) + p.items.size() * sizeof(Item) +
+                   p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
+  return p;
+}
+
+void check_host_series(const double* s, int64_t n, const char* name) {
+  if (!s) fail(CCM_E_INVAL, std::string(name) + " is NULL");
+  for (int64_t t = 0; t < n; ++t)
+    if (!std::isfinite(s[t]) || std::fabs(s[t]) > 1e17)
+      fail(CCM_E_INVAL, std::string(name) + " has a non-finite or too large value");
+}
+
+Spec make_spec(int64_t N, const int32_t* E, int32_t nE, const int32_t* tau, int32_t ntau,
+               const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
+               const ccm_opts* opts) {
+  if (!E || !tau || !L) fail(CCM_E_INVAL, "NULL parameter array");
+  if (nE < 1 || ntau < 1 || nL < 1) fail(CCM_E_INVAL, "nE, ntau and nL must be >= 1");
+  Spec s;
+  s.N = N;
+  s.E.assign(E, E + nE);
+  s.tau.assign(tau, tau + ntau);
+  s.L.assign(L, L + nL);
+  s.r = r;
+  s.seed = seed;
+  if (opts) {
+    s.excl = opts->exclusion_radius;
+    s.query_set = opts->query_set;
+    s.flags = opts->flags;
+  }
+  return s;
+}
+
+
+}  // namespace ccmh

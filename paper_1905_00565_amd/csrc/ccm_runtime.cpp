@@ -1,6 +1,6 @@
-// ccm_runtime.cpp -- host runtime of libccm: validation, planning of the
-// realization / work-item lists, device buffers, HIP graph capture and
-// replay, and the C ABI declared in include/ccm.h.
+// ccm_runtime.cpp -- host runtime of libccm: device state of a plan, HIP
+// graph capture and replay, profiling, and the C ABI declared in
+// include/ccm.h (the server is in ccm_server.cpp).
 //
 // A call is planned once per distinct shape (series length, E and tau grid,
 // L list, r, seed, options).  The plan's descriptors and buffers live on the
@@ -9,442 +9,10 @@
 // Exec's own series buffer (host-to-device, or device-to-device for the
 // device-pointer forms) and results copied out, so the graph never refers to
 // caller memory.
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <memory>
-#include <mutex>
-#include <new>
-#include <string>
-#include <vector>
+#include "ccm_host.h"
+#include "ccm_context.h"
 
-#include "ccm.h"
-#include "ccm_internal.h"
-
-using namespace ccmk;
-
-namespace {
-
-// ---------------------------------------------------------------------------
-// errors
-// ---------------------------------------------------------------------------
-
-struct Fail {
-  ccm_status status;
-  std::string what;
-};
-
-[[noreturn]] void fail(ccm_status st, const std::string& what) { throw Fail{st, what}; }
-
-void hip_check(hipError_t e, const char* expr) {
-  if (e == hipSuccess) return;
-  const ccm_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
-                            ? CCM_E_NOMEM
-                            : CCM_E_DEVICE;
-  fail(st, std::string(expr) + ": " + hipGetErrorString(e));
-}
-
-#define HIPCHK(expr) hip_check((expr), #expr)
-
-// ---------------------------------------------------------------------------
-// device buffers
-// ---------------------------------------------------------------------------
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  void ensure(size_t n) {
-    if (n <= bytes && p) return;
-    release();
-    if (n == 0) n = 256;
-    HIPCHK(hipMalloc(&p, n));
-    bytes = n;
-  }
-  template <class T>
-  T* as() const { return static_cast<T*>(p); }
-};
-
-template <class T>
-void upload(DevBuf& b, const std::vector<T>& v) {
-  b.ensure(v.size() * sizeof(T));
-  if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-}
-
-// ---------------------------------------------------------------------------
-// plans
-// ---------------------------------------------------------------------------
-
-struct Spec {
-  int32_t M = 0;      // 0: a pair of series (X, Y); M >= 2: causal matrix of M series
-  int64_t N = 0;
-  std::vector<int32_t> E, tau;
-  std::vector<int64_t> L;
-  int32_t r = 0;
-  uint64_t seed = 0;
-  int32_t excl = 0;
-  int32_t query_set = 0;
-  uint32_t flags = 0;
-
-  bool operator==(const Spec& o) const {
-    return M == o.M && N == o.N && E == o.E && tau == o.tau && L == o.L && r == o.r &&
-           seed == o.seed && excl == o.excl && query_set == o.query_set &&
-           (flags & ~CCM_FLAG_NO_GRAPH) == (o.flags & ~CCM_FLAG_NO_GRAPH);
-  }
-};
-
-int excl_mode(int32_t excl) {
-  if (excl == 0) return kExclSelf;
-  if (excl < 0) return kKeepSelf;
-  return kWindow;
-}
-
-int64_t min_library(int32_t E, int32_t excl) {
-  const int64_t w = excl < 0 ? 0 : 2 * (int64_t)excl + 1;
-  return (int64_t)E + 1 + w;
-}
-
-struct Plan {
-  Spec spec;
-  int mode = kExclSelf;
-  int window = 0;
-  std::vector<IngestJob> ingest;
-  int64_t n64 = 0, n32 = 0;
-  std::vector<EmbedJob> embed;
-  int64_t n_emb = 0, max_embed = 0;
-  int64_t n_qord = 0;                 // query-order entries (sum of n_e)
-  int32_t n_series = 2;               // series sorted (segments)
-  std::vector<int32_t> seg_off;       // segment offsets of the value sort
-  size_t sort_temp = 0;
-  std::vector<SampleJob> sample;
-  int64_t n_lib = 0;
-  std::vector<GatherJob> gather;
-  int64_t n_pts = 0;                  // floats of ordered library coordinates
-  int64_t n_pj = 0;                   // ordered library indices
-  int64_t max_sorted_n_e = 0;
-  std::vector<Realization> rz;
-  std::vector<int32_t> self_of;       // matrix: searched series of each realization
-  // realization r owns sample job rz_sample[r] and gather job r
-  std::vector<int64_t> rz_sample;
-  // batched items grouped by E, longest library first within a group
-  std::vector<Item> items;
-  int e_first[kMaxE + 1] = {0};
-  int e_count[kMaxE + 1] = {0};
-  int64_t n_slots = 0;
-  int64_t n_out = 0;
-  std::vector<int64_t> L_eff;   // per (iE, itau, iL)
-  double pairs = 0, flops = 0, preds = 0;
-  size_t device_bytes = 0;
-};
-
-// Validate a sweep and lay out every realization of it.
-Plan make_plan(const Spec& s) {
-  if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
-  if (s.E.empty() || s.tau.empty() || s.L.empty()) fail(CCM_E_INVAL, "empty E, tau or L list");
-  if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
-  if (s.query_set != 0 && s.query_set != 1) fail(CCM_E_INVAL, "query_set must be 0 or 1");
-  if (s.N > (int64_t)INT32_MAX / 2) fail(CCM_E_INVAL, "N too large");
-  for (int32_t e : s.E)
-    if (e < 1 || e > kMaxE) fail(CCM_E_INVAL, "E must be in [1, 10]");
-  for (int32_t t : s.tau)
-    if (t < 1) fail(CCM_E_INVAL, "tau must be >= 1");
-  for (int32_t e : s.E)
-    for (int32_t t : s.tau) {
-      const int64_t ne = s.N - (int64_t)(e - 1) * t;
-      if (ne < e + 2) fail(CCM_E_INVAL, "N_e = N - (E-1) tau must be >= E + 2");
-      for (int64_t l : s.L) {
-        if (l < e + 2) fail(CCM_E_INVAL, "every L must be >= E + 2");
-        if (std::min(l, ne) < min_library(e, s.excl))
-          fail(CCM_E_INVAL, "library too small for the exclusion window");
-      }
-    }
-
-  Plan p;
-  p.spec = s;
-  p.mode = excl_mode(s.excl);
-  p.window = s.excl > 0 ? s.excl : 0;
-  const int nE = (int)s.E.size(), nT = (int)s.tau.size(), nL = (int)s.L.size();
-  const int64_t N = s.N;
-  p.n64 = 2 * N;
-  p.n32 = 2 * N;
-  p.ingest.push_back({0, 0, 2 * N});
-  p.n_series = 2;
-  p.seg_off = {0, (int32_t)N, (int32_t)(2 * N)};
-  const int64_t sorted_limit = gather_max_sorted_n_e();
-  p.n_out = 2LL * nE * nT * nL * s.r;
-  p.L_eff.assign((size_t)nE * nT * nL, 0);
-
-  for (int ie = 0; ie < nE; ++ie) {
-    const int32_t E = s.E[ie];
-    const int Q = crossmap_queries_per_lane(E, false);
-    const int64_t qt = (int64_t)kBlock * Q;
-    for (int it = 0; it < nT; ++it) {
-      const int32_t tau = s.tau[it];
-      const int64_t ne = N - (int64_t)(E - 1) * tau;
-      int64_t emb_off[2], qord_off[2];
-      for (int sr = 0; sr < 2; ++sr) {
-        emb_off[sr] = p.n_emb;
-        qord_off[sr] = p.n_qord;
-        p.embed.push_back({sr * N, p.n_emb, sr * N, p.n_qord, ne, N, E, tau});
-        p.n_emb += ne * E;
-        p.n_qord += ne;
-        p.max_embed = std::max(p.max_embed, ne * E);
-      }
-      const int32_t sorted = ne <= sorted_limit ? 1 : 0;
-      if (sorted) p.max_sorted_n_e = std::max(p.max_sorted_n_e, ne);
-      for (int il = 0; il < nL; ++il) {
-        const int64_t le = std::min(s.L[il], ne);
-        p.L_eff[((size_t)ie * nT + it) * nL + il] = le;
-        for (int ri = 0; ri < s.r; ++ri) {
-          const int64_t lib_off = p.n_lib;
-          p.sample.push_back({s.seed, ne, le, lib_off, E, tau, ri, 0});
-          p.n_lib += le;
-          for (int dir = 0; dir < 2; ++dir) {
-            // dir 0: library Y (series 1) predicts X (series 0); dir 1: reverse
-            const int lib_s = dir == 0 ? 1 : 0;
-            const int tgt_s = dir == 0 ? 0 : 1;
-            Realization R{};
-            R.emb_off = emb_off[lib_s];
-            R.pts_off = p.n_pts;
-            R.pj_off = p.n_pj;
-            R.qord_off = qord_off[lib_s];
-            R.tgt_off = tgt_s * N;
-            R.E = E;
-            R.tau = tau;
-            R.n_e = (int32_t)ne;
-            R.l_eff = (int32_t)le;
-            R.n_query = (int32_t)(s.query_set ? le : ne);
-            R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
-            R.slot_base = p.n_slots;
-            R.out_index = ((((int64_t)dir * nE + ie) * nT + it) * nL + il) * s.r + ri;
-            GatherJob gj{};
-            gj.emb_off = R.emb_off;
-            gj.lib_off = lib_off;
-            gj.order_off = lib_s * N;
-            gj.pts_off = R.pts_off;
-            gj.pj_off = R.pj_off;
-            gj.start_off = R.slot_base;
-            gj.l_eff = le;
-            gj.n_e = ne;
-            gj.n_series = N;
-            gj.E = E;
-            gj.tau = tau;
-            gj.qt = (int32_t)qt;
-            gj.query_set = s.query_set;
-            gj.sorted = sorted;
-            p.gather.push_back(gj);
-            p.n_pts += le * E;
-            p.n_pj += le;
-            p.n_slots += R.n_tiles;
-            p.rz.push_back(R);
-            p.rz_sample.push_back((int64_t)p.sample.size() - 1);
-            // algorithmic work: every (query, candidate) pair but the query itself
-            const double nq = (double)R.n_query;
-            double pairs = nq * (double)le;
-            if (p.mode == kExclSelf) pairs -= s.query_set ? nq : (double)le;
-            p.pairs += pairs;
-            p.flops += pairs * (3.0 * E - 1.0);
-            p.preds += nq;
-          }
-        }
-      }
-    }
-  }
-  if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
-
-  // Items grouped by E; within a group the longest libraries go first.
-  std::vector<int32_t> order(p.rz.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    if (p.rz[a].E != p.rz[b].E) return p.rz[a].E < p.rz[b].E;
-    return p.rz[a].l_eff > p.rz[b].l_eff;
-  });
-  for (int32_t idx : order) {
-    const Realization& R = p.rz[idx];
-    if (p.e_count[R.E] == 0) p.e_first[R.E] = (int)p.items.size();
-    for (int t = 0; t < R.n_tiles; ++t) p.items.push_back({idx, t});
-    p.e_count[R.E] += R.n_tiles;
-  }
-  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
-
-  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
-                     p.n_series, nullptr, nullptr));
-  p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
-                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 + p.sort_temp +
-                   (size_t)p.n32 * 12 +
-                   p.n_slots * sizeof(Moments) + p.n_out * 8 +
-                   p.rz.size() * sizeof(Realization) + p.items.size() * sizeof(Item) +
-                   p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
-  return p;
-}
-
-// Causal matrix: M series, one (E, tau); libraries per (L, r) shared by every
-// series; one realization per (searched series, L, r) predicting all others.
-Plan make_plan_matrix(const Spec& s) {
-  if (s.M < 2) fail(CCM_E_INVAL, "M must be >= 2");
-  if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
-  if (s.L.empty()) fail(CCM_E_INVAL, "empty L list");
-  if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
-  if (s.query_set != 0 && s.query_set != 1) fail(CCM_E_INVAL, "query_set must be 0 or 1");
-  if ((int64_t)s.M * s.N > (int64_t)INT32_MAX / 2) fail(CCM_E_INVAL, "M*N too large");
-  const int32_t E = s.E[0], tau = s.tau[0];
-  if (E < 1 || E > kMaxE) fail(CCM_E_INVAL, "E must be in [1, 10]");
-  if (tau < 1) fail(CCM_E_INVAL, "tau must be >= 1");
-  const int64_t N = s.N;
-  const int64_t ne = N - (int64_t)(E - 1) * tau;
-  if (ne < E + 2) fail(CCM_E_INVAL, "N_e = N - (E-1) tau must be >= E + 2");
-  for (int64_t l : s.L) {
-    if (l < E + 2) fail(CCM_E_INVAL, "every L must be >= E + 2");
-    if (std::min(l, ne) < min_library(E, s.excl))
-      fail(CCM_E_INVAL, "library too small for the exclusion window");
-  }
-  Plan p;
-  p.spec = s;
-  p.mode = excl_mode(s.excl);
-  p.window = s.excl > 0 ? s.excl : 0;
-  const int M = s.M, nL = (int)s.L.size();
-  p.n64 = (int64_t)M * N;
-  p.n32 = (int64_t)M * N;
-  p.ingest.push_back({0, 0, (int64_t)M * N});
-  p.n_series = M;
-  for (int a = 0; a <= M; ++a) p.seg_off.push_back((int32_t)(a * N));
-  p.n_out = (int64_t)M * M * nL * s.r;
-  p.L_eff.assign(nL, 0);
-  const int Q = crossmap_queries_per_lane(E, false);
-  const int64_t qt = (int64_t)kBlock * Q;
-  const int32_t sorted = ne <= gather_max_sorted_n_e() ? 1 : 0;
-  if (sorted) p.max_sorted_n_e = ne;
-  std::vector<int64_t> emb_off(M), qord_off(M);
-  for (int a = 0; a < M; ++a) {
-    emb_off[a] = p.n_emb;
-    qord_off[a] = p.n_qord;
-    p.embed.push_back({a * N, p.n_emb, a * N, p.n_qord, ne, N, E, tau});
-    p.n_emb += ne * E;
-    p.n_qord += ne;
-    p.max_embed = std::max(p.max_embed, ne * E);
-  }
-  std::vector<int64_t> lib_off((size_t)nL * s.r);
-  for (int il = 0; il < nL; ++il) {
-    const int64_t le = std::min(s.L[il], ne);
-    p.L_eff[il] = le;
-    for (int ri = 0; ri < s.r; ++ri) {
-      lib_off[(size_t)il * s.r + ri] = p.n_lib;
-      p.sample.push_back({s.seed, ne, le, p.n_lib, E, tau, ri, 0});
-      p.n_lib += le;
-    }
-  }
-  for (int a = 0; a < M; ++a)
-    for (int il = 0; il < nL; ++il)
-      for (int ri = 0; ri < s.r; ++ri) {
-        const int64_t le = p.L_eff[il];
-        Realization R{};
-        R.emb_off = emb_off[a];
-        R.pts_off = p.n_pts;
-        R.pj_off = p.n_pj;
-        R.qord_off = qord_off[a];
-        R.tgt_off = 0;
-        R.E = E;
-        R.tau = tau;
-        R.n_e = (int32_t)ne;
-        R.l_eff = (int32_t)le;
-        R.n_query = (int32_t)(s.query_set ? le : ne);
-        R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
-        R.slot_base = p.n_slots;
-        R.out_index = (((int64_t)a * M) * nL + il) * s.r + ri;   // target 0 of row a
-        GatherJob gj{};
-        gj.emb_off = R.emb_off;
-        gj.lib_off = lib_off[(size_t)il * s.r + ri];
-        gj.order_off = a * N;
-        gj.pts_off = R.pts_off;
-        gj.pj_off = R.pj_off;
-        gj.start_off = R.slot_base;
-        gj.l_eff = le;
-        gj.n_e = ne;
-        gj.n_series = N;
-        gj.E = E;
-        gj.tau = tau;
-        gj.qt = (int32_t)qt;
-        gj.query_set = s.query_set;
-        gj.sorted = sorted;
-        p.gather.push_back(gj);
-        p.n_pts += le * E;
-        p.n_pj += le;
-        p.n_slots += R.n_tiles;
-        p.rz.push_back(R);
-        p.self_of.push_back(a);
-        p.rz_sample.push_back((int64_t)il * s.r + ri);
-        const double nq = (double)R.n_query;
-        double pairs = nq * (double)le;
-        if (p.mode == kExclSelf) pairs -= s.query_set ? nq : (double)le;
-        p.pairs += pairs;
-        p.flops += pairs * (3.0 * E - 1.0);
-        p.preds += nq * (M - 1);
-      }
-  std::vector<int32_t> order(p.rz.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return p.rz[x].l_eff > p.rz[y].l_eff; });
-  p.e_first[E] = 0;
-  for (int32_t idx : order)
-    for (int t = 0; t < p.rz[idx].n_tiles; ++t) p.items.push_back({idx, t});
-  p.e_count[E] = (int)p.items.size();
-  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
-  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
-                     p.n_series, nullptr, nullptr));
-  p.device_bytes = p.n64 * 8 + p.n32 * 16 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
-                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 + p.sort_temp +
-                   p.n_slots * M * multi_sums_bytes() + p.n_out * 8 +
-                   p.rz.size() * (sizeof(Realization) + 4) + p.items.size() * sizeof(Item) +
-                   p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
-  return p;
-}
-
-// ---------------------------------------------------------------------------
-// execution state of one plan
-// ---------------------------------------------------------------------------
-
-struct EvPair {
-  hipEvent_t a = nullptr, b = nullptr;
-};
-
-struct Exec {
-  Plan plan;
-  DevBuf d_ingest, d_embed, d_sample, d_gather, d_rz, d_items, d_plain_items;
-  DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_pj, d_partial, d_out, d_counter;
-  DevBuf d_iota, d_keys_out, d_order, d_segoff, d_sort_temp, d_qord, d_start, d_self;
-  std::vector<int64_t> plain_first;   // per realization: first plain item
-  hipGraphExec_t graph = nullptr;
-  ~Exec() {
-    if (graph) (void)hipGraphExecDestroy(graph);
-  }
-};
-
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-
-struct ccm_ctx {
-  int device = 0;
-  int num_cus = 0;
-  hipStream_t stream = nullptr;
-  std::mutex mu;
-  std::string err;
-  bool profiling = false;
-  std::vector<EvPair> ev_pending, ev_free;
-  ccm_profile prof{};
-  std::unique_ptr<Exec> exec;   // the most recent plan
-};
+using namespace ccmh;
 
 namespace {
 
@@ -687,53 +255,6 @@ void run(ccm_ctx* c, Exec* ex, hipStream_t st) {
   }
 }
 
-void check_host_series(const double* s, int64_t n, const char* name) {
-  if (!s) fail(CCM_E_INVAL, std::string(name) + " is NULL");
-  for (int64_t t = 0; t < n; ++t)
-    if (!std::isfinite(s[t]) || std::fabs(s[t]) > 1e17)
-      fail(CCM_E_INVAL, std::string(name) + " has a non-finite or too large value");
-}
-
-Spec make_spec(int64_t N, const int32_t* E, int32_t nE, const int32_t* tau, int32_t ntau,
-               const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
-               const ccm_opts* opts) {
-  if (!E || !tau || !L) fail(CCM_E_INVAL, "NULL parameter array");
-  if (nE < 1 || ntau < 1 || nL < 1) fail(CCM_E_INVAL, "nE, ntau and nL must be >= 1");
-  Spec s;
-  s.N = N;
-  s.E.assign(E, E + nE);
-  s.tau.assign(tau, tau + ntau);
-  s.L.assign(L, L + nL);
-  s.r = r;
-  s.seed = seed;
-  if (opts) {
-    s.excl = opts->exclusion_radius;
-    s.query_set = opts->query_set;
-    s.flags = opts->flags;
-  }
-  return s;
-}
-
-template <class F>
-ccm_status guarded(ccm_ctx* c, F&& f) {
-  if (!c) return CCM_E_INVAL;
-  std::lock_guard<std::mutex> lock(c->mu);
-  c->err.clear();
-  try {
-    HIPCHK(hipSetDevice(c->device));
-    f();
-    return CCM_OK;
-  } catch (const Fail& e) {
-    c->err = e.what;
-    return e.status;
-  } catch (const std::bad_alloc&) {
-    c->err = "host allocation failed";
-    return CCM_E_NOMEM;
-  } catch (...) {
-    c->err = "unexpected error";
-    return CCM_E_DEVICE;
-  }
-}
 
 }  // namespace
 

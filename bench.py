@@ -11,8 +11,9 @@ The series are resident in device memory before the timed region starts.
 
 Prints one JSON line: value = cross-map predictions per second, plus
 rho-realizations per second, the roofline of the cross-map kernel (binary32
-flops per pair 3E-1, over the summed HIP-event duration of its launches) and
-the CPU oracle timed on a bounded random sample of the same realizations.
+flops per pair 3E-1, over the summed HIP-event duration of its launches), the
+served form's p50/p99 job latency on a Poisson job stream (`served`), and the
+CPU oracle timed on a bounded random sample of the same realizations.
 """
 from __future__ import annotations
 
@@ -42,6 +43,10 @@ def parse():
     ap.add_argument("--flags", type=int, default=0, help="CCM_FLAG_* bits")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=32,
+                    help="jobs in the served leg (0: skip it)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of measured capacity")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device to device "
                          "once (a plain copy of known size for calibrating the "
@@ -83,6 +88,73 @@ def cpu_baseline(w, budget_s):
             "sample": f"{done} realizations drawn uniformly at random (seed 12345) from "
                       f"the {len(grid) * w.r * 2} of the workload, {el:.1f} s on "
                       f"{threads} threads"}
+
+
+def served_leg(ctx, n_jobs, load, seed=4):
+    """Served form on the job-stream workload: capacity from a closed loop
+    (all jobs submitted at once), then an open loop of Poisson arrivals at
+    `load` x capacity for p50/p99 latency.  Comparisons: the same jobs one
+    after another through ccm() (each call batched), and the first few
+    through ccm() with one launch per realization (the unbatched form)."""
+    stream = synth.job_stream(n_jobs, 1.0, seed=seed)
+    jobs = []
+    for j in stream:
+        X, Y = j["make"]()
+        jobs.append((X, Y, j))
+
+    def run(srv, arrivals):
+        t0 = time.perf_counter()
+        tickets = []
+        for (X, Y, j), ta in zip(jobs, arrivals):
+            delay = ta - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append((srv.submit(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"]), j))
+        lat, preds = [], 0.0
+        for t, j in tickets:
+            assert srv.wait(t) == capi.CCM_OK
+            _, _, st = srv.result(t, len(j["L"]), j["r"])
+            lat.append(st["t_done"] - st["t_submit"])
+            preds += st["predictions"]
+        return time.perf_counter() - t0, np.asarray(lat), preds
+
+    with capi.Server(ctx) as srv:
+        run(srv, [0.0] * min(4, n_jobs))                      # warm the server up
+        make_closed, lat_closed, preds = run(srv, [0.0] * n_jobs)
+        capacity = n_jobs / make_closed
+        rate = load * capacity
+        gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n_jobs)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        make_open, lat_open, _ = run(srv, list(arrivals))
+    per_job = []
+    for X, Y, j in jobs:
+        t0 = time.perf_counter()
+        ctx.ccm(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"])
+        per_job.append(time.perf_counter() - t0)
+    fifo = sum(per_job)
+    n_plain = min(3, n_jobs)
+    t0 = time.perf_counter()
+    for X, Y, j in jobs[:n_plain]:
+        ctx.ccm(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"], flags=capi.CCM_FLAG_PLAIN)
+    fifo_plain = time.perf_counter() - t0
+    return {
+        "workload": f"{n_jobs} jobs: coupled-logistic pairs, N~U[1000,50000], E~U[1,10], "
+                    "tau~U[1,4], 10-point geometric L grid, r=100",
+        "capacity_jobs_per_sec": capacity,
+        "closed_loop_predictions_per_sec": preds / make_closed,
+        "arrival_rate_jobs_per_sec": rate,
+        "load": load,
+        "p50_latency_ms": float(np.percentile(lat_open, 50) * 1e3),
+        "p99_latency_ms": float(np.percentile(lat_open, 99) * 1e3),
+        "mean_latency_ms": float(lat_open.mean() * 1e3),
+        "open_loop_jobs_per_sec": n_jobs / make_open,
+        "fifo_ccm_jobs_per_sec": n_jobs / fifo,
+        "served_over_fifo": (n_jobs / make_closed) / (n_jobs / fifo),
+        "plain_subset_jobs": n_plain,
+        "plain_subset_seconds": fifo_plain,
+        "batched_subset_seconds": sum(per_job[:n_plain]),
+        "batched_over_plain": fifo_plain / sum(per_job[:n_plain]),
+    }
 
 
 def main():
@@ -174,6 +246,10 @@ def main():
             "pairs_per_step": prof["pairs"] / a.steps,
         },
     }
+    if a.serve_jobs > 0:
+        print(f"bench: served leg, {a.serve_jobs} jobs", file=sys.stderr, flush=True)
+        ctx.profile_enable(False)
+        out["served"] = served_leg(ctx, a.serve_jobs, a.serve_load)
     if a.cpu_seconds > 0:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)

@@ -141,7 +141,9 @@ double item_cost(const Realization& R, int tile, int qt) {
 struct ccm_server {
   ccm_ctx* ctx = nullptr;
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // job preparation and finalize
+  hipStream_t estream[2] = {nullptr, nullptr};   // epochs alternate between these
+  hipEvent_t prep_ev = nullptr;      // after the latest preparation
   double epoch_ms = 20.0;
   int max_jobs = 64;
   // device memory
@@ -150,7 +152,11 @@ struct ccm_server {
   RangeAlloc arena_alloc, slot_alloc, rz_alloc;
   // host staging for epoch items (pinned)
   Item* items_host[2] = {nullptr, nullptr};
-  hipEvent_t epoch_ev[2] = {nullptr, nullptr};
+  hipEvent_t epoch_ev[2] = {nullptr, nullptr};     // end of each in-flight epoch
+  hipEvent_t epoch_ev0[2] = {nullptr, nullptr};    // start of its kernels
+  double last_end_host = -1.0;                     // host time the last epoch was seen done
+  double epoch_cost[2] = {0.0, 0.0};
+  size_t min_items = 8192;                         // keep the GPU full within an epoch
   bool epoch_busy[2] = {false, false};
   int64_t epoch_count = 0;
   double lane_ops_per_ms = 4.0e10;   // throughput estimate, refined online
@@ -267,6 +273,8 @@ void start_job(ccm_server* s, Job& j) {
 // Queue the merge of a job's moments and the copy of its rho to the host.
 void finish_job(ccm_server* s, Job& j) {
   const Plan& p = j.plan;
+  // the job's items may be in the latest epoch of either epoch stream
+  for (int b = 0; b < 2; ++b) HIPCHK(hipStreamWaitEvent(s->stream, s->epoch_ev[b], 0));
   HIPCHK(launch_finalize(s->rz_table.as<Realization>() + j.rz0, (int64_t)p.rz.size(),
                          s->slots_partial.as<Moments>(), at<double>(s, j.region + j.lay.out),
                          s->stream));
@@ -316,13 +324,32 @@ void scheduler_loop(ccm_server* s) {
         j.t_admit = s->now();
         s->active.push_back(j.ticket);
         start_job(s, j);
+        HIPCHK(hipEventRecord(s->prep_ev, s->stream));
       }
-      // 3. build an epoch: items of admitted jobs, oldest first, up to the budget
+      // 3. build an epoch: items of admitted jobs, oldest first, up to the
+      // budget.  Two epochs may be in flight: this buffer's previous epoch is
+      // waited for (and timed) only now, so the GPU runs the other one while
+      // the host prepares this one.
       if (s->epoch_busy[buf]) {
         lk.unlock();
         HIPCHK(hipEventSynchronize(s->epoch_ev[buf]));
+        // epochs overlap on two streams: the time an epoch adds is measured
+        // end to end (from the previous epoch's completion, or its own start)
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, s->epoch_ev0[buf], s->epoch_ev[buf]));
+        const double t_end = s->now();
+        if (s->last_end_host >= 0.0) {
+          const double gap = (t_end - s->last_end_host) * 1e3;
+          if (gap > 0.0 && gap < ms) ms = (float)gap;
+        }
+        s->last_end_host = t_end;
         lk.lock();
         s->epoch_busy[buf] = false;
+        if (ms > 0.5f) {
+          const double rate = std::min(2.0e11, std::max(1.0e10, s->epoch_cost[buf] / ms));
+          s->lane_ops_per_ms = 0.7 * s->lane_ops_per_ms + 0.3 * rate;
+        }
+        continue;   // re-check retirements and admissions first
       }
       const double budget = s->epoch_ms * s->lane_ops_per_ms;
       double cost = 0.0;
@@ -337,8 +364,8 @@ void scheduler_loop(ccm_server* s) {
         const int qt = kBlock * crossmap_queries_per_lane(E, false);
         const GroupKey key{E, p.mode, p.spec.query_set, p.window};
         auto& g = groups[key];
-        while (j.next_item < p.items.size() && (cost < budget || n_items == 0) &&
-               n_items < s->items_cap) {
+        while (j.next_item < p.items.size() &&
+               (cost < budget || n_items < s->min_items) && n_items < s->items_cap) {
           const Item it = p.items[j.next_item++];
           cost += item_cost(p.rz[it.rz], it.tile, qt);
           g.push_back({(int32_t)(j.rz0 + it.rz), it.tile});
@@ -346,12 +373,14 @@ void scheduler_loop(ccm_server* s) {
         }
         j.last_epoch = g.empty() ? j.last_epoch : s->epoch_count;
         if (j.next_item == p.items.size()) completes.push_back(&j);
-        if (cost >= budget || n_items >= s->items_cap) break;
+        if ((cost >= budget && n_items >= s->min_items) || n_items >= s->items_cap) break;
       }
       // jobs cancelled while active finish once their in-flight items are done
       for (uint64_t t : s->active) {
         Job& j = *s->jobs[t];
         if (j.state == kCancelled && !j.finishing) {
+          for (int b = 0; b < 2; ++b)
+            HIPCHK(hipStreamWaitEvent(s->stream, s->epoch_ev[b], 0));
           HIPCHK(hipEventRecord(j.done_ev, s->stream));
           j.finishing = true;
         }
@@ -379,11 +408,11 @@ void scheduler_loop(ccm_server* s) {
         std::copy(kv.second.begin(), kv.second.end(), s->items_host[buf] + pos);
         pos += kv.second.size();
       }
+      hipStream_t es = s->estream[buf];
+      HIPCHK(hipStreamWaitEvent(es, s->prep_ev, 0));   // inputs of newly admitted jobs
       HIPCHK(hipMemcpyAsync(s->items_dev[buf].p, s->items_host[buf], pos * sizeof(Item),
-                            hipMemcpyHostToDevice, s->stream));
-      hipEvent_t ev0 = nullptr;
-      HIPCHK(hipEventCreate(&ev0));
-      HIPCHK(hipEventRecord(ev0, s->stream));
+                            hipMemcpyHostToDevice, es));
+      HIPCHK(hipEventRecord(s->epoch_ev0[buf], es));
       pos = 0;
       float* fa = static_cast<float*>(s->arena.p);
       int32_t* ia = static_cast<int32_t*>(s->arena.p);
@@ -397,23 +426,15 @@ void scheduler_loop(ccm_server* s) {
                                s->items_dev[buf].as<Item>() + pos, n, nullptr, fa, fa, ia, ia,
                                s->slots_start.as<int32_t>(), da,
                                s->slots_partial.as<Moments>(), kv.first.qs, kv.first.window,
-                               nodump, s->stream));
+                               nodump, es));
         pos += n;
       }
-      HIPCHK(hipEventRecord(s->epoch_ev[buf], s->stream));
+      HIPCHK(hipEventRecord(s->epoch_ev[buf], es));
       s->epoch_busy[buf] = true;
+      s->epoch_cost[buf] = cost;
       for (Job* j : completes)
         if (!j->finishing && j->state != kCancelled) finish_job(s, *j);
       ++s->epoch_count;
-      // refine the throughput estimate from this epoch once it is done
-      lk.unlock();
-      HIPCHK(hipEventSynchronize(s->epoch_ev[buf]));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, ev0, s->epoch_ev[buf]));
-      (void)hipEventDestroy(ev0);
-      lk.lock();
-      s->epoch_busy[buf] = false;
-      if (ms > 0.5f) s->lane_ops_per_ms = 0.7 * s->lane_ops_per_ms + 0.3 * (cost / ms);
       buf ^= 1;
     } catch (const Fail& e) {
       s->fatal = e.what;
@@ -474,8 +495,20 @@ ccm_status ccm_server_create(ccm_ctx* c, const ccm_server_cfg* cfg, ccm_server**
       HIPCHK(hipHostMalloc((void**)&s->items_host[b], s->items_cap * sizeof(Item),
                            hipHostMallocDefault));
       HIPCHK(hipEventCreate(&s->epoch_ev[b]));
+      HIPCHK(hipEventCreate(&s->epoch_ev0[b]));
     }
     HIPCHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK(hipStreamCreateWithFlags(&s->estream[b], hipStreamNonBlocking));
+      HIPCHK(hipEventRecord(s->epoch_ev[b], s->estream[b]));   // waitable from the start
+    }
+    HIPCHK(hipEventCreate(&s->prep_ev));
+    {
+      hipDeviceProp_t prop;
+      HIPCHK(hipGetDeviceProperties(&prop, c->device));
+      s->min_items = (size_t)std::max(1, prop.multiProcessorCount) * 32;
+    }
+    HIPCHK(hipEventRecord(s->prep_ev, s->stream));
   } catch (const Fail& e) {
     {
       std::lock_guard<std::mutex> lock(c->mu);
@@ -484,6 +517,7 @@ ccm_status ccm_server_create(ccm_ctx* c, const ccm_server_cfg* cfg, ccm_server**
     for (int b = 0; b < 2; ++b) {
       if (s->items_host[b]) (void)hipHostFree(s->items_host[b]);
       if (s->epoch_ev[b]) (void)hipEventDestroy(s->epoch_ev[b]);
+      if (s->epoch_ev0[b]) (void)hipEventDestroy(s->epoch_ev0[b]);
     }
     return e.status;
   }
@@ -614,6 +648,8 @@ void ccm_server_destroy(ccm_server* s) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
+  for (int b = 0; b < 2; ++b)
+    if (s->estream[b]) (void)hipStreamSynchronize(s->estream[b]);
   for (auto& kv : s->jobs) {
     if (kv.second->rho_host) (void)hipHostFree(kv.second->rho_host);
     if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
@@ -621,8 +657,12 @@ void ccm_server_destroy(ccm_server* s) {
   for (int b = 0; b < 2; ++b) {
     if (s->items_host[b]) (void)hipHostFree(s->items_host[b]);
     if (s->epoch_ev[b]) (void)hipEventDestroy(s->epoch_ev[b]);
+    if (s->epoch_ev0[b]) (void)hipEventDestroy(s->epoch_ev0[b]);
   }
   (void)hipStreamDestroy(s->stream);
+  for (int b = 0; b < 2; ++b)
+    if (s->estream[b]) (void)hipStreamDestroy(s->estream[b]);
+  if (s->prep_ev) (void)hipEventDestroy(s->prep_ev);
   delete s;
 }
 

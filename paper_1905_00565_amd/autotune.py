@@ -1,0 +1,201 @@
+"""Pick the cross-map kernel's launch shape for each embedding dimension E.
+
+The hot kernel has two shape parameters per E (see ``csrc/ccm_tune.h``):
+Q, the queries each lane holds, and G, the library candidates evaluated per
+trigger check.  Both are compile-time, so candidates are separate builds of
+the kernel translation unit.  Each build ("column") gives every E one
+candidate from that E's list; every column is timed on the same sweep and
+each E keeps its fastest candidate.
+
+Two phases, so that compilation stays off the GPU host:
+
+    python -m paper_1905_00565_amd.autotune build          # CPU: compile columns
+    python -m paper_1905_00565_amd.autotune time --out T.h  # GPU: time, write table
+
+``time`` runs one child process per column (a process loads one libccm) and
+writes the chosen table as a header in the format of ``csrc/ccm_tune.h``,
+plus a JSON report next to it.  Results do not depend on the shape (the
+neighbour selection is exact whatever the visiting order and grouping), so
+the choice is about speed alone.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+from . import build as B
+
+TUNE_DIR = os.path.join(B.PKG, "_tune")
+
+# (Q, G) candidates per E; the first is the hand-picked starting point.
+CANDIDATES = {
+    1: [(4, 16), (4, 8), (2, 16), (4, 12)],
+    2: [(4, 8), (4, 16), (4, 4), (2, 8)],
+    3: [(4, 8), (4, 4), (2, 8), (3, 8)],
+    4: [(4, 8), (4, 4), (2, 8), (3, 8)],
+}
+for _e in range(5, 11):
+    CANDIDATES[_e] = [(2, 4), (4, 4), (3, 4), (2, 3), (3, 3), (4, 3)]
+
+
+def columns():
+    n = max(len(v) for v in CANDIDATES.values())
+    cols = []
+    for k in range(n):
+        q = [0] + [CANDIDATES[e][min(k, len(CANDIDATES[e]) - 1)][0] for e in range(1, 11)]
+        g = [0] + [CANDIDATES[e][min(k, len(CANDIDATES[e]) - 1)][1] for e in range(1, 11)]
+        cols.append((q, g))
+    return cols
+
+
+def _brace(v):
+    return "{" + ", ".join(str(x) for x in v) + "}"
+
+
+def _build_column(k, q, g):
+    obj = os.path.join(TUNE_DIR, f"kernels_{k}.o")
+    cmd = [B.hipcc(), *B.common_flags(), f"-DCCM_TUNE_Q={_brace(q)}", f"-DCCM_TUNE_G={_brace(g)}",
+           "-c", os.path.join(B.CSRC, "ccm_kernels.hip"), "-o", obj]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"hipcc failed on column {k}")
+    others = [os.path.join(B.BUILD, os.path.splitext(s)[0] + ".o")
+              for s in B.SOURCES if s != "ccm_kernels.hip"]
+    lib = os.path.join(TUNE_DIR, f"libccm_{k}.so")
+    res = subprocess.run([B.hipcc(), f"--offload-arch={B.ARCH}", "-shared", "-fPIC", "-o", lib,
+                          obj, *others], capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"link failed on column {k}")
+    os.remove(obj)
+    return lib
+
+
+def build_columns(jobs: int = 8):
+    B.build_library()                       # the other objects, and a current library
+    os.makedirs(TUNE_DIR, exist_ok=True)
+    cols = columns()
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        libs = list(ex.map(lambda a: _build_column(*a), [(k, q, g) for k, (q, g) in enumerate(cols)]))
+    with open(os.path.join(TUNE_DIR, "columns.json"), "w") as f:
+        json.dump({"columns": cols, "libs": [os.path.basename(x) for x in libs]}, f)
+    return libs
+
+
+def time_column(r: int, n: int):
+    """Child process: time every E of the sweep with the library in CCM_LIBRARY."""
+    import torch
+    from . import capi, synth
+    w = synth.workload_sweep(n=n, r=r)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.X, device=dev)
+    Y = torch.tensor(w.Y, device=dev)
+    ctx = capi.Context(0)
+    ctx.profile_enable(True)
+    out = {}
+    for e in w.E:
+        rho = torch.empty((2, 1, len(w.tau), len(w.L), r), dtype=torch.float64, device=dev)
+        st = torch.cuda.current_stream()
+        ctx.ccm_sweep_dev(X, Y, [e], w.tau, w.L, r, w.seed, rho, stream=st)
+        torch.cuda.synchronize()
+        ctx.profile_read(reset=True)
+        ctx.ccm_sweep_dev(X, Y, [e], w.tau, w.L, r, w.seed, rho, stream=st)
+        torch.cuda.synchronize()
+        p = ctx.profile_read(reset=True)
+        out[e] = {"ms": p["kernel_ms"], "flops": p["flops"], "rho_sum": float(rho.sum().item())}
+        print(f"E={e} {p['kernel_ms']:.2f} ms", file=sys.stderr, flush=True)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def write_header(path, q, g, note):
+    text = f"""// ccm_tune.h -- launch shape of the cross-map kernel for each embedding
+// dimension E (index 0 unused).  Written by paper_1905_00565_amd/autotune.py
+// from timings of the E = 1..10, tau = 1..5 sweep on coupled-logistic series
+// ({note}); the build may override either table with -DCCM_TUNE_Q={{...}}
+// or -DCCM_TUNE_G={{...}} (the tuner does, to time candidates).
+//
+//   kTuneQ[E]  queries per lane (a workgroup of 256 lanes holds 256*Q queries)
+//   kTuneG[E]  library candidates per trigger check (one group of G distances
+//              per query, then one compare against its running E+1-th key)
+#pragma once
+
+#ifndef CCM_TUNE_Q
+#define CCM_TUNE_Q {_brace(q)}
+#endif
+#ifndef CCM_TUNE_G
+#define CCM_TUNE_G {_brace(g)}
+#endif
+
+namespace ccmk {{
+constexpr int kTuneQ[11] = CCM_TUNE_Q;
+constexpr int kTuneG[11] = CCM_TUNE_G;
+}}  // namespace ccmk
+"""
+    with open(path, "w") as f:
+        f.write(text)
+
+
+def time_columns(out: str, r: int, n: int, timeout: int):
+    with open(os.path.join(TUNE_DIR, "columns.json")) as f:
+        meta = json.load(f)
+    cols, libs = meta["columns"], meta["libs"]
+    results = []
+    for k, lib in enumerate(libs):
+        print(f"column {k}: Q={cols[k][0][1:]} G={cols[k][1][1:]}", flush=True)
+        env = dict(os.environ, CCM_LIBRARY=os.path.join(TUNE_DIR, lib))
+        res = subprocess.run([sys.executable, "-u", "-m", "paper_1905_00565_amd.autotune",
+                              "_child", "--r", str(r), "--n", str(n)],
+                             env=env, capture_output=True, text=True, timeout=timeout,
+                             cwd=B.ROOT)
+        if res.returncode != 0:
+            sys.stderr.write(res.stderr[-4000:])
+            raise RuntimeError(f"column {k} failed (exit {res.returncode})")
+        results.append({int(e): v for e, v in json.loads(res.stdout.strip().splitlines()[-1]).items()})
+    # every column must give the same rho (the shape changes only the speed)
+    for e in range(1, 11):
+        sums = {results[k][e]["rho_sum"] for k in range(len(results))}
+        if len({round(s, 9) for s in sums}) != 1:
+            raise RuntimeError(f"rho differs between columns at E={e}: {sums}")
+    q, g, report = [0], [0], {}
+    for e in range(1, 11):
+        ms = [results[k][e]["ms"] for k in range(len(results))]
+        best = min(range(len(ms)), key=lambda k: ms[k])
+        q.append(cols[best][0][e])
+        g.append(cols[best][1][e])
+        report[e] = {"choice": [q[-1], g[-1]], "ms": ms,
+                     "candidates": [[cols[k][0][e], cols[k][1][e]] for k in range(len(cols))],
+                     "tflops": results[best][e]["flops"] / ms[best] / 1e9}
+    write_header(out, q, g, f"N = {n}, r = {r} per (E, tau, L)")
+    with open(os.path.splitext(out)[0] + ".json", "w") as f:
+        json.dump(report, f, indent=1)
+    for e in range(1, 11):
+        print(f"E={e}: Q={q[e]} G={g[e]}  {min(report[e]['ms']):.2f} ms "
+              f"({report[e]['tflops']:.1f} TFLOP/s)  candidates ms={['%.2f' % x for x in report[e]['ms']]}")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("phase", choices=["build", "time", "_child"])
+    ap.add_argument("--out", default=os.path.join(B.CSRC, "ccm_tune.h"))
+    ap.add_argument("--r", type=int, default=50)
+    ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--jobs", type=int, default=8)
+    ap.add_argument("--timeout", type=int, default=240)
+    a = ap.parse_args(argv)
+    if a.phase == "build":
+        for lib in build_columns(a.jobs):
+            print("built", lib)
+    elif a.phase == "time":
+        time_columns(a.out, a.r, a.n, a.timeout)
+    else:
+        time_column(a.r, a.n)
+
+
+if __name__ == "__main__":
+    main()

@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIBRARY = os.path.join(_HERE, "libccm.so")
+# CCM_LIBRARY may name another build of the same library (e.g. a tuning variant).
+LIBRARY = os.environ.get("CCM_LIBRARY") or os.path.join(_HERE, "libccm.so")
 
 CCM_OK = 0
 CCM_E_INVAL = -1

@@ -115,8 +115,10 @@ struct Plan {
   std::vector<EmbedJob> embed;
   int64_t n_emb = 0, max_embed = 0;
   int64_t n_qord = 0;                 // query-order entries (sum of n_e)
-  int32_t n_series = 2;               // series sorted (segments)
-  std::vector<int32_t> seg_off;       // segment offsets of the value sort
+  std::vector<OrderJob> orders;       // order sets (each a sort segment of N)
+  int32_t n_sets = 0;
+  std::vector<int32_t> seg_off;       // segment offsets of the order sort
+  int64_t n_ord = 0;                  // n_sets * N
   size_t sort_temp = 0;
   std::vector<SampleJob> sample;
   int64_t n_lib = 0;
@@ -138,6 +140,10 @@ struct Plan {
   double pairs = 0, flops = 0, preds = 0;
   size_t device_bytes = 0;
 };
+
+// Order set of (series, tau) -- tau 0 for the value order -- created on
+// first use; returns its offset in the order pool.
+int64_t order_set(Plan& p, int series, int32_t tau);
 
 // Validate a sweep (pair of series, E x tau grid) and lay out every
 // realization of it.

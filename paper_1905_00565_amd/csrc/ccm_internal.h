@@ -8,10 +8,11 @@ namespace ccmk {
 
 constexpr int kMaxE = 10;          // simplex embedding dimension range is 1..10
 constexpr int kBlock = 256;        // threads per workgroup of the cross-map kernel
+constexpr int kWaves = kBlock / 64; // wavefronts per workgroup (one scan start each)
 
 // Exclusion handling of the cross-map kernel (compile-time variants).
 enum ExclMode : int {
-  kExclSelf = 0,    // drop the query itself (keep E+2 running slots, drop self after)
+  kExclSelf = 0,    // drop the query itself (rejected when it would be inserted)
   kKeepSelf = 1,    // every library point is a candidate
   kWindow = 2,      // drop candidates with |j - i| <= w (per-pair mask)
 };
@@ -23,14 +24,29 @@ struct IngestJob {
   int64_t n;
 };
 
+// One visiting order of a series' embedded points (an "order set"): indices
+// i sorted by a key.  An embedded point i of any E has its oldest lag
+// coordinate at time i, so one set serves every E with the same delay; each
+// embedding keeps the indices below its own n_e.  tau == 0: the value S[i]
+// (used for E = 1); tau > 0: the position on a Hilbert curve over the two
+// oldest lag coordinates (S[i], S[i + tau]), each scaled to 16 bits by the
+// series' range (used for E >= 2 with that delay; i >= n - tau sorts last
+// and is never an embedded point).
+struct OrderJob {
+  int64_t src_off;   // floats into the FP32 series pool
+  int64_t key_off;   // uint32 keys (and the sorted order) of this set
+  int64_t n;         // series length
+  int32_t tau;
+  int32_t pad;
+};
+
 // One embedding of one series.
 //   emb[i*E + k] = s[i + (E-1)tau - k tau]           (AoS float [n_e][E])
-//   qord[p]      = embedded points in ascending order of their first
-//                  coordinate (the series value at their time)
+//   qord[p]      = embedded points in the visiting order of the set
 struct EmbedJob {
   int64_t src_off;   // floats into the FP32 series pool
   int64_t dst_off;   // floats into the embedding pool
-  int64_t order_off; // int32 into the series-order pool (n_series entries)
+  int64_t order_off; // int32 into the order pool (its order set, n_series entries)
   int64_t qord_off;  // int32 into the query-order pool (n_e entries)
   int64_t n_e;
   int64_t n_series;
@@ -50,16 +66,16 @@ struct SampleJob {
   int32_t pad;
 };
 
-// One library gather: the library of one realization laid out in ascending
-// order of the first coordinate (pts AoS [l_eff][E], pj the embedded index
+// One library gather: the library of one realization laid out in visiting
+// order (pts AoS [l_eff][E], pj the embedded index
 // of each), plus the library position each query tile starts scanning from.
 struct GatherJob {
   int64_t emb_off;   // floats: embedding of the library series
   int64_t lib_off;   // int32: library indices (ascending index order)
-  int64_t order_off; // int32: order of the library series' values
+  int64_t order_off; // int32: order set of the library embedding
   int64_t pts_off;   // floats: output coordinates
   int64_t pj_off;    // int32: output embedded indices
-  int64_t start_off; // int32: output scan start per query tile
+  int64_t start_off; // int32: output scan start per wavefront of each query tile
   int64_t l_eff;
   int64_t n_e;
   int64_t n_series;
@@ -84,7 +100,7 @@ struct Realization {
   int32_t l_eff;     // library size
   int32_t n_query;   // queries: n_e, or l_eff when only library points are queried
   int32_t n_tiles;   // query tiles (= work items) of this realization
-  int64_t slot_base; // first partial-moment slot (one per tile; also scan starts)
+  int64_t slot_base; // first partial-moment slot (one per tile; scan starts kWaves per slot)
   int64_t out_index; // where rho goes in the caller's output
 };
 
@@ -114,6 +130,8 @@ hipError_t launch_embed(const EmbedJob* jobs, int n_jobs, int64_t max_n,
                         const float* s32, float* emb, hipStream_t st);
 hipError_t launch_iota_segments(int32_t* out, int64_t n_series, int32_t segs,
                                 hipStream_t st);
+hipError_t launch_order_keys(const OrderJob* jobs, int n_jobs, const float* s32,
+                             uint32_t* keys, hipStream_t st);
 hipError_t launch_query_order(const EmbedJob* jobs, int n_jobs,
                               const int32_t* order, int32_t* qord, hipStream_t st);
 hipError_t launch_sample(const SampleJob* jobs, int64_t n_jobs, int32_t* out,
@@ -146,11 +164,10 @@ hipError_t launch_finalize_multi(const Realization* rzs, const int32_t* self_of,
                                  int64_t out_stride_b, double* out, hipStream_t st);
 size_t multi_sums_bytes();
 
-// Series value order (ccm_sort.hip): per segment of n_series values, the
-// time indices sorted by value (stable).  temp_bytes is queried with
-// temp == nullptr.
-hipError_t sort_series(void* temp, size_t& temp_bytes, const float* keys_in,
-                       float* keys_out, const int32_t* idx_in, int32_t* idx_out,
+// Order sets (ccm_sort.hip): per segment of n_series keys, the time indices
+// sorted by key (stable).  temp_bytes is queried with temp == nullptr.
+hipError_t sort_series(void* temp, size_t& temp_bytes, const uint32_t* keys_in,
+                       uint32_t* keys_out, const int32_t* idx_in, int32_t* idx_out,
                        int64_t n_series, int32_t segs, const int32_t* seg_offsets,
                        hipStream_t st);
 

@@ -10,10 +10,12 @@
 // Kernels, in pipeline order:
 //   k_ingest       double series -> float series (round to nearest even)
 //   k_embed        lagged-coordinate embedding, AoS float[n_e][E]
-//   (sort_series)  each series' time indices in ascending order of value
-//   k_query_order  embedded points in ascending order of first coordinate
+//   k_order_keys   visiting-order keys of each order set (value, or Hilbert
+//                  position over the two oldest lag coordinates)
+//   (sort_series)  each order set's embedded indices sorted by key
+//   k_query_order  each embedding's points in its set's visiting order
 //   k_sample       library subsamples: selection sampling driven by SplitMix64
-//   k_gather       each library laid out in first-coordinate order, plus the
+//   k_gather       each library laid out in visiting order, plus the
 //                  position every query tile starts scanning from
 //   k_crossmap     fused distance / top-(E+1) / prediction / Pearson moments,
 //                  one workgroup per (realization, query tile) work item,
@@ -26,10 +28,12 @@
 //   the same value), no other contraction (-ffp-contract=off);
 //   neighbours are the first E+1 candidates in (d2, j) order.
 // The order in which candidates are visited is free: selection uses the exact
-// (d2, j) key.  Queries are grouped and candidates visited nearest first (in
-// the first coordinate) only so that the running lists settle early and the
-// insertion path stays rare; every (query, candidate) pair is still evaluated.
+// (d2, j) key.  Queries are grouped and candidates visited roughly nearest
+// first (along a space-filling curve) only so that the running lists settle
+// early and the insertion path stays rare; every (query, candidate) pair is
+// still evaluated.
 #include "ccm_internal.h"
+#include "ccm_tune.h"
 
 namespace ccmk {
 
@@ -70,6 +74,78 @@ __global__ void k_iota_segments(int32_t* __restrict__ out, int64_t n, int64_t to
     out[x] = (int32_t)(x % n);
 }
 
+// Position of (x, y) on the Hilbert curve filling [0, 2^16)^2 (the classic
+// quadrant-by-quadrant construction: at each scale the quadrant contributes
+// s*s*((3*rx) ^ ry) and the remaining coordinates are reflected/swapped into
+// that quadrant's frame).
+__device__ __forceinline__ uint32_t hilbert16(uint32_t x, uint32_t y) {
+  uint32_t d = 0;
+  for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u;
+    const uint32_t ry = (y & s) ? 1u : 0u;
+    d += s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = 0xffffu - x;
+        y = 0xffffu - y;
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
+}
+
+// Order-preserving map of binary32 to uint32.
+__device__ __forceinline__ uint32_t ordered_bits(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Keys of one order set (see OrderJob).  One workgroup per set: the series'
+// range first (for the 16-bit scaling), then one key per time point.
+__global__ __launch_bounds__(256) void k_order_keys(const OrderJob* __restrict__ jobs,
+                                                    const float* __restrict__ s32,
+                                                    uint32_t* __restrict__ keys) {
+  __shared__ float s_lo[256], s_hi[256];
+  const OrderJob J = jobs[blockIdx.x];
+  const float* __restrict__ s = s32 + J.src_off;
+  uint32_t* __restrict__ k = keys + J.key_off;
+  const int tid = threadIdx.x;
+  if (J.tau == 0) {
+    for (int64_t t = tid; t < J.n; t += 256) k[t] = ordered_bits(s[t]);
+    return;
+  }
+  float lo = __builtin_inff(), hi = -__builtin_inff();
+  for (int64_t t = tid; t < J.n; t += 256) {
+    lo = fminf(lo, s[t]);
+    hi = fmaxf(hi, s[t]);
+  }
+  s_lo[tid] = lo;
+  s_hi[tid] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      s_lo[tid] = fminf(s_lo[tid], s_lo[tid + w]);
+      s_hi[tid] = fmaxf(s_hi[tid], s_hi[tid + w]);
+    }
+    __syncthreads();
+  }
+  lo = s_lo[0];
+  const float span = s_hi[0] - lo;
+  const float scale = span > 0.f ? 65535.f / span : 0.f;
+  for (int64_t i = tid; i < J.n; i += 256) {
+    if (i >= J.n - J.tau) {
+      k[i] = 0xffffffffu;
+      continue;
+    }
+    const uint32_t x = (uint32_t)fminf(65535.f, fmaxf(0.f, (s[i] - lo) * scale));
+    const uint32_t y = (uint32_t)fminf(65535.f, fmaxf(0.f, (s[i + J.tau] - lo) * scale));
+    k[i] = hilbert16(x, y);
+  }
+}
+
 // Exclusive rank of this thread among the flagged threads of its 256-thread
 // workgroup, and the workgroup total, in thread order.
 __device__ __forceinline__ int block_rank(bool flag, int* s_wave, int& total) {
@@ -92,9 +168,8 @@ __device__ __forceinline__ int block_rank(bool flag, int* s_wave, int& total) {
   return before + r;
 }
 
-// Embedded points in ascending order of their first coordinate: the series
-// order restricted to times >= (E-1) tau, shifted to embedded indices.
-// One workgroup per embedding.
+// Embedded points in visiting order: the order set restricted to indices
+// below n_e.  One workgroup per embedding.
 __global__ __launch_bounds__(kBlock) void k_query_order(
     const EmbedJob* __restrict__ jobs, const int32_t* __restrict__ order_pool,
     int32_t* __restrict__ qord_pool) {
@@ -102,15 +177,14 @@ __global__ __launch_bounds__(kBlock) void k_query_order(
   const EmbedJob J = jobs[blockIdx.x];
   const int32_t* __restrict__ ord = order_pool + J.order_off;
   int32_t* __restrict__ q = qord_pool + J.qord_off;
-  const int64_t off = (int64_t)(J.E - 1) * J.tau;
   int64_t out = 0;
   for (int64_t base = 0; base < J.n_series; base += kBlock) {
     const int64_t k = base + threadIdx.x;
-    const int64_t t = k < J.n_series ? ord[k] : -1;
-    const bool f = t >= off;
+    const int64_t i = k < J.n_series ? ord[k] : J.n_e;
+    const bool f = i < J.n_e;
     int total;
     const int r = block_rank(f, s_wave, total);
-    if (f) q[out + r] = (int32_t)(t - off);
+    if (f) q[out + r] = (int32_t)i;
     out += total;
   }
 }
@@ -157,14 +231,15 @@ __global__ void k_sample(const SampleJob* __restrict__ jobs, int64_t n_jobs,
   for (; s < J.l_eff; ++s, ++j) out[s] = (int32_t)j;
 }
 
-// The library of one realization, laid out contiguously in ascending order
-// of the first coordinate (coordinates AoS and embedded indices), so the scan
+// The library of one realization, laid out contiguously in visiting order
+// (coordinates AoS and embedded indices), so the scan
 // streams it through the scalar cache with no dependent index load.  For each
-// query tile (tiles take consecutive queries in the same order) it records
-// the library position of the tile's middle query: the scan starts there and
-// works outward.  One workgroup per job; the library's membership bitmask
-// lives in LDS (dynamic size).  Jobs marked unsorted keep ascending index
-// order and start every tile at position 0.
+// wavefront of each query tile (a wavefront takes a run of consecutive
+// queries in the same order) it records the library position of the run's
+// middle query: that wavefront's scan starts there and works outward.  One
+// workgroup per job; the library's membership bitmask lives in LDS (dynamic
+// size).  Jobs marked unsorted keep ascending index order and start every
+// scan at position 0.
 __global__ __launch_bounds__(kBlock) void k_gather(
     const GatherJob* __restrict__ jobs, const float* __restrict__ emb_pool,
     const int32_t* __restrict__ lib_pool, const int32_t* __restrict__ order_pool,
@@ -189,8 +264,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     }
     for (int64_t c = tid; c < J.l_eff; c += kBlock) pj[c] = lib[c];
     if (J.query_set == 0) {
-      const int64_t tiles = (J.n_e + J.qt - 1) / J.qt;
-      for (int64_t t = tid; t < tiles; t += kBlock) start[t] = 0;
+      const int64_t n_start = (J.n_e + J.qt - 1) / J.qt * kWaves;
+      for (int64_t t = tid; t < n_start; t += kBlock) start[t] = 0;
     }
     return;
   }
@@ -205,14 +280,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(
   __syncthreads();
 
   const int32_t* __restrict__ ord = order_pool + J.order_off;
-  const int64_t off = (int64_t)(E - 1) * J.tau;
   int64_t pf = 0;   // embedded points passed so far (in order)
   int64_t pl = 0;   // library points passed so far (in order)
   for (int64_t base = 0; base < J.n_series; base += kBlock) {
     const int64_t k = base + tid;
-    const int64_t t = k < J.n_series ? ord[k] : -1;
-    const bool fo = t >= off;
-    const int64_t i = fo ? t - off : 0;
+    const int64_t t = k < J.n_series ? ord[k] : J.n_e;
+    const bool fo = t < J.n_e;
+    const int64_t i = fo ? t : 0;
     const bool fl = fo && ((bits[i >> 5] >> (i & 31)) & 1u);
     int tot_o, tot_l;
     const int ro = block_rank(fo, s_wave[0], tot_o);
@@ -223,10 +297,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(
       for (int kk = 0; kk < E; ++kk) pts[c * E + kk] = emb[i * E + kk];
     }
     if (fo && J.query_set == 0) {
+      // wavefront w of tile t takes query positions [s*sub, (s+1)*sub) with
+      // s = t*kWaves + w; its scan starts at its middle query
+      const int64_t sub = J.qt / kWaves;
       const int64_t p = pf + ro;
-      const int64_t tile = p / J.qt;
-      const int64_t anchor = min(tile * J.qt + J.qt / 2, J.n_e - 1);
-      if (p == anchor) start[tile] = (int32_t)(pl + rl);
+      const int64_t sw = p / sub;
+      const int64_t anchor = min(sw * sub + sub / 2, J.n_e - 1);
+      if (p == anchor) start[sw] = (int32_t)(pl + rl);
     }
     pf += tot_o;
     pl += tot_l;
@@ -331,43 +408,68 @@ __device__ __forceinline__ Moments mom_merge(const Moments& a, const Moments& b)
 // the fused cross-map item
 // ---------------------------------------------------------------------------
 
-// Library candidates per trigger check; the group's coordinates (G*E values,
-// uniform across the wavefront) come through the scalar cache into SGPRs.
+// Library candidates per trigger check (tuned per E); the group's
+// coordinates (G*E values, uniform across the wavefront) come through the
+// scalar cache into SGPRs.
 template <int E>
 struct Group {
-  static constexpr int G = E <= 2 ? 8 : (E <= 4 ? 4 : 2);
+  static constexpr int G = kTuneG[E];
 };
 
+// Running list length: the E+1 neighbours.  With self excluded the query
+// itself is rejected when it would be inserted, so it never takes a slot.
 template <int E, int MODE>
 struct Slots {
-  static constexpr int KS = MODE == kExclSelf ? E + 2 : E + 1;
+  static constexpr int KS = E + 1;
 };
 
-// Distances from the lane's queries to library positions c..c+G-1, then one
-// compare per query against its running (KS)-th best; only when some lane
-// of the wavefront qualifies are the candidates inserted.
-template <int E, int Q, int MODE, int G>
-__device__ __forceinline__ void scan_group(
-    const float* __restrict__ pts, const int32_t* __restrict__ pj, int c,
-    const float (&qc)[Q][E], const int (&qi)[Q], int window,
-    double (&key)[Q][Slots<E, MODE>::KS]) {
-  constexpr int KS = Slots<E, MODE>::KS;
+// G consecutive library candidates (uniform across the wavefront: loaded
+// through the scalar cache into SGPRs).
+template <int E, int G>
+struct Chunk {
   float p[G][E];
   int32_t j[G];
+};
+
+template <int E, int G>
+__device__ __forceinline__ void load_chunk(Chunk<E, G>& ch, const float* __restrict__ pts,
+                                           const int32_t* __restrict__ pj, int c) {
 #pragma unroll
   for (int g = 0; g < G; ++g) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) p[g][k] = pts[(int64_t)(c + g) * E + k];
-    j[g] = pj[c + g];
+    for (int k = 0; k < E; ++k) ch.p[g][k] = pts[(int64_t)(c + g) * E + k];
+    ch.j[g] = pj[c + g];
   }
+}
+
+// Make the chunk's values available at this point (the wait for its scalar
+// loads happens here, before anything issued after it).
+template <int E, int G>
+__device__ __forceinline__ void settle_chunk(const Chunk<E, G>& ch) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) asm volatile("" ::"s"(ch.p[g][k]));
+    asm volatile("" ::"s"(ch.j[g]));
+  }
+}
+
+// Distances from the lane's queries to the chunk's candidates, then one
+// compare per query against its running (KS)-th best; only when some lane
+// of the wavefront qualifies are the candidates inserted.
+template <int E, int Q, int MODE, int G>
+__device__ __forceinline__ void compute_chunk(
+    const Chunk<E, G>& ch, const float (&qc)[Q][E], const int (&qi)[Q], int window,
+    double (&key)[Q][Slots<E, MODE>::KS]) {
+  constexpr int KS = Slots<E, MODE>::KS;
   float d2[G][Q];
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
-      float v = sqdist<E>(qc[m], p[g]);
+      float v = sqdist<E>(qc[m], ch.p[g]);
       if (MODE == kWindow) {
-        const int dj = j[g] - qi[m];
+        const int dj = ch.j[g] - qi[m];
         if (dj <= window && dj >= -window) v = __builtin_nanf("");
       }
       d2[g][m] = v;
@@ -380,10 +482,20 @@ __device__ __forceinline__ void scan_group(
     if (__builtin_amdgcn_ballot_w64(mn <= key_d2(key[m][KS - 1]))) {
 #pragma unroll
       for (int g = 0; g < G; ++g)
-        if (d2[g][m] <= key_d2(key[m][KS - 1]))
-          insert_key<KS>(key[m], make_key(d2[g][m], j[g]));
+        if (d2[g][m] <= key_d2(key[m][KS - 1]) && (MODE != kExclSelf || ch.j[g] != qi[m]))
+          insert_key<KS>(key[m], make_key(d2[g][m], ch.j[g]));
     }
   }
+}
+
+template <int E, int Q, int MODE, int G>
+__device__ __forceinline__ void scan_group(
+    const float* __restrict__ pts, const int32_t* __restrict__ pj, int c,
+    const float (&qc)[Q][E], const int (&qi)[Q], int window,
+    double (&key)[Q][Slots<E, MODE>::KS]) {
+  Chunk<E, G> ch;
+  load_chunk<E, G>(ch, pts, pj, c);
+  compute_chunk<E, Q, MODE, G>(ch, qc, qi, window, key);
 }
 
 // Queries of one item and their running candidate lists after the scan of
@@ -404,19 +516,26 @@ __device__ __forceinline__ void scan_library(
   constexpr int KS = Slots<E, MODE>::KS;
   constexpr int G = Group<E>::G;
   constexpr int QT = kBlock * Q;                    // queries per tile
-  const int tid = threadIdx.x;
+  constexpr int QW = 64 * Q;                        // queries per wavefront
+  // the wavefront index is uniform: say so, so that the scan position and
+  // the library addresses stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const float* __restrict__ emb = emb_pool + R.emb_off;
   const float* __restrict__ pts = pts_pool + R.pts_off;
   const int32_t* __restrict__ pj = pj_pool + R.pj_off;
   const int32_t* __restrict__ qord = qord_pool + R.qord_off;
   const int L = R.l_eff;
 
-  // queries of this lane: positions tile*QT + m*kBlock + tid of the query
-  // order (every embedded point, or the ordered library itself)
+  // queries of this lane: positions tile*QT + wave*QW + m*64 + lane of the
+  // query order (every embedded point, or the ordered library itself), so
+  // that each wavefront holds a run of QW consecutive queries
+  bool any = false;
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
-    const int qq = tile * QT + m * kBlock + tid;
+    const int qq = tile * QT + wave * QW + m * 64 + lane;
     const bool valid = qq < R.n_query;
+    any |= valid;
     const int i = valid ? (query_set ? pj[qq] : qord[qq]) : 0;
     S.qi[m] = valid ? i : -1;
 #pragma unroll
@@ -427,54 +546,56 @@ __device__ __forceinline__ void scan_library(
 #pragma unroll
     for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
 
-  // Brute-force scan of every library position, outward from the tile's
-  // start: groups alternate forward [f, f+G) and backward [b-G, b); single
-  // positions finish both ends.
-  int s0 = query_set ? min(tile * QT + QT / 2, L - 1) : start_pool[R.slot_base + tile];
+  // A wavefront with no query (the tail of the last tile) has nothing to scan.
+  if (!__builtin_amdgcn_ballot_w64(any)) return;
+
+  // Brute-force scan of every library position, outward from the
+  // wavefront's start s0: a forward group [f, f+G) and a backward group
+  // [b-G, b) per step while both fit, then the remaining groups of the
+  // longer side, then single positions at both ends.
+  int s0 = query_set ? min(tile * QT + wave * QW + QW / 2, L - 1)
+                     : start_pool[(R.slot_base + tile) * kWaves + wave];
   s0 = min(max(s0, 0), L);
   int f = s0, b = s0;
-  bool fwd = true;
-  for (;;) {
-    const bool can_f = f + G <= L;
-    const bool can_b = b - G >= 0;
-    if (!can_f && !can_b) break;
-    const bool take_f = can_f && (fwd || !can_b);
-    const int c = take_f ? f : b - G;
-    if (take_f) f += G;
-    else b -= G;
-    fwd = !fwd;
-    scan_group<E, Q, MODE, G>(pts, pj, c, S.qc, S.qi, window, S.key);
+  const int both = min((L - s0) / G, s0 / G);
+  // Software pipeline over the scalar loads: a chunk's loads are issued one
+  // chunk ahead, and each chunk is waited for before the next is requested
+  // (scalar loads return out of order, so a wait covers all that are
+  // outstanding).
+  if (both > 0) {
+    Chunk<E, G> A, B;
+    load_chunk<E, G>(A, pts, pj, f);
+    for (int k = 0; k < both; ++k) {
+      settle_chunk<E, G>(A);
+      __builtin_amdgcn_sched_barrier(0);
+      load_chunk<E, G>(B, pts, pj, b - G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute_chunk<E, Q, MODE, G>(A, S.qc, S.qi, window, S.key);
+      f += G;
+      settle_chunk<E, G>(B);
+      __builtin_amdgcn_sched_barrier(0);
+      load_chunk<E, G>(A, pts, pj, k + 1 < both ? f : f - G);
+      __builtin_amdgcn_sched_barrier(0);
+      compute_chunk<E, Q, MODE, G>(B, S.qc, S.qi, window, S.key);
+      b -= G;
+    }
   }
+  for (; f + G <= L; f += G) scan_group<E, Q, MODE, G>(pts, pj, f, S.qc, S.qi, window, S.key);
+  for (; b - G >= 0; b -= G) scan_group<E, Q, MODE, G>(pts, pj, b - G, S.qc, S.qi, window, S.key);
   for (; f < L; ++f) scan_group<E, Q, MODE, 1>(pts, pj, f, S.qc, S.qi, window, S.key);
   for (; b > 0; --b) scan_group<E, Q, MODE, 1>(pts, pj, b - 1, S.qc, S.qi, window, S.key);
 }
 
-// The E+1 neighbours of query m (nearest first) from its running list.
+// The E+1 neighbours of query m (nearest first): its running list.  Every
+// slot holds a real candidate (the library has at least E+1 candidates
+// besides the excluded ones).
 template <int E, int Q, int MODE>
 __device__ __forceinline__ void select_neighbors(const ScanState<E, Q, MODE>& S, int m,
                                                  float (&nd)[E + 1], int32_t (&nj)[E + 1]) {
-  constexpr int K = E + 1;
-  constexpr int KS = Slots<E, MODE>::KS;
-  if (MODE == kExclSelf) {
-    // the query itself is at most one of the KS keys (every slot holds a
-    // real candidate: the library has at least KS points); without it the
-    // first K of the others are the neighbours
-    int pos = KS - 1;
 #pragma unroll
-    for (int s = KS - 1; s >= 0; --s)
-      if (key_j(S.key[m][s]) == S.qi[m]) pos = s;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const double kk = t < pos ? S.key[m][t] : S.key[m][t + 1];
-      nd[t] = key_d2(kk);
-      nj[t] = key_j(kk);
-    }
-  } else {
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      nd[t] = key_d2(S.key[m][t]);
-      nj[t] = key_j(S.key[m][t]);
-    }
+  for (int t = 0; t < E + 1; ++t) {
+    nd[t] = key_d2(S.key[m][t]);
+    nj[t] = key_j(S.key[m][t]);
   }
 }
 
@@ -788,11 +909,11 @@ struct QSet {
   }
 };
 
-// Queries per lane for the hot kernel, per E (fewer when the running lists
-// are long so that registers stay within budget).
+// Queries per lane for the hot kernel (tuned per E: fewer when the running
+// lists are long so that registers stay within budget).
 template <int E>
 struct DefaultQ {
-  static constexpr int Q = E <= 4 ? 4 : 2;
+  static constexpr int Q = kTuneQ[E];
 };
 
 static CrossmapFn crossmap_kernel(int E, int mode, bool dump, int* q_out) {
@@ -849,6 +970,13 @@ hipError_t launch_iota_segments(int32_t* out, int64_t n_series, int32_t segs,
   const int64_t total = n_series * segs;
   if (total <= 0) return hipSuccess;
   k_iota_segments<<<blocks_for(total, 256), 256, 0, st>>>(out, n_series, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_order_keys(const OrderJob* jobs, int n_jobs, const float* s32,
+                             uint32_t* keys, hipStream_t st) {
+  if (n_jobs <= 0) return hipSuccess;
+  k_order_keys<<<n_jobs, 256, 0, st>>>(jobs, s32, keys);
   return hipGetLastError();
 }
 

@@ -4,6 +4,20 @@
 
 namespace ccmh {
 
+int64_t order_set(Plan& p, int series, int32_t tau) {
+  const int64_t N = p.spec.N;
+  for (size_t k = 0; k < p.orders.size(); ++k)
+    if (p.orders[k].src_off == series * N && p.orders[k].tau == tau) return p.orders[k].key_off;
+  const int64_t off = (int64_t)p.orders.size() * N;
+  p.orders.push_back({series * N, off, N, tau, 0});
+  p.n_sets = (int32_t)p.orders.size();
+  p.n_ord = p.n_sets * N;
+  if (p.n_ord > (int64_t)INT32_MAX) fail(CCM_E_INVAL, "too many time points to order");
+  p.seg_off.clear();
+  for (int k = 0; k <= p.n_sets; ++k) p.seg_off.push_back((int32_t)(k * N));
+  return off;
+}
+
 // Validate a sweep and lay out every realization of it.
 Plan make_plan(const Spec& s) {
   if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
@@ -35,8 +49,6 @@ Plan make_plan(const Spec& s) {
   p.n64 = 2 * N;
   p.n32 = 2 * N;
   p.ingest.push_back({0, 0, 2 * N});
-  p.n_series = 2;
-  p.seg_off = {0, (int32_t)N, (int32_t)(2 * N)};
   const int64_t sorted_limit = gather_max_sorted_n_e();
   p.n_out = 2LL * nE * nT * nL * s.r;
   p.L_eff.assign((size_t)nE * nT * nL, 0);
@@ -48,11 +60,12 @@ Plan make_plan(const Spec& s) {
     for (int it = 0; it < nT; ++it) {
       const int32_t tau = s.tau[it];
       const int64_t ne = N - (int64_t)(E - 1) * tau;
-      int64_t emb_off[2], qord_off[2];
+      int64_t emb_off[2], qord_off[2], ord_off[2];
       for (int sr = 0; sr < 2; ++sr) {
         emb_off[sr] = p.n_emb;
         qord_off[sr] = p.n_qord;
-        p.embed.push_back({sr * N, p.n_emb, sr * N, p.n_qord, ne, N, E, tau});
+        ord_off[sr] = order_set(p, sr, E == 1 ? 0 : tau);
+        p.embed.push_back({sr * N, p.n_emb, ord_off[sr], p.n_qord, ne, N, E, tau});
         p.n_emb += ne * E;
         p.n_qord += ne;
         p.max_embed = std::max(p.max_embed, ne * E);
@@ -87,10 +100,10 @@ Plan make_plan(const Spec& s) {
             GatherJob gj{};
             gj.emb_off = R.emb_off;
             gj.lib_off = lib_off;
-            gj.order_off = lib_s * N;
+            gj.order_off = ord_off[lib_s];
             gj.pts_off = R.pts_off;
             gj.pj_off = R.pj_off;
-            gj.start_off = R.slot_base;
+            gj.start_off = R.slot_base * kWaves;
             gj.l_eff = le;
             gj.n_e = ne;
             gj.n_series = N;
@@ -135,10 +148,10 @@ Plan make_plan(const Spec& s) {
   if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
 
   HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
-                     p.n_series, nullptr, nullptr));
+                     p.n_sets, nullptr, nullptr));
   p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
-                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 + p.sort_temp +
-                   (size_t)p.n32 * 12 +
+                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
+                   (size_t)p.n_ord * 16 +
                    p.n_slots * sizeof(Moments) + p.n_out * 8 +
                    p.rz.size() * sizeof(Realization) + p.items.size() * sizeof(Item) +
                    p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
@@ -173,19 +186,18 @@ Plan make_plan_matrix(const Spec& s) {
   p.n64 = (int64_t)M * N;
   p.n32 = (int64_t)M * N;
   p.ingest.push_back({0, 0, (int64_t)M * N});
-  p.n_series = M;
-  for (int a = 0; a <= M; ++a) p.seg_off.push_back((int32_t)(a * N));
   p.n_out = (int64_t)M * M * nL * s.r;
   p.L_eff.assign(nL, 0);
   const int Q = crossmap_queries_per_lane(E, false);
   const int64_t qt = (int64_t)kBlock * Q;
   const int32_t sorted = ne <= gather_max_sorted_n_e() ? 1 : 0;
   if (sorted) p.max_sorted_n_e = ne;
-  std::vector<int64_t> emb_off(M), qord_off(M);
+  std::vector<int64_t> emb_off(M), qord_off(M), ord_off(M);
   for (int a = 0; a < M; ++a) {
     emb_off[a] = p.n_emb;
     qord_off[a] = p.n_qord;
-    p.embed.push_back({a * N, p.n_emb, a * N, p.n_qord, ne, N, E, tau});
+    ord_off[a] = order_set(p, a, E == 1 ? 0 : tau);
+    p.embed.push_back({a * N, p.n_emb, ord_off[a], p.n_qord, ne, N, E, tau});
     p.n_emb += ne * E;
     p.n_qord += ne;
     p.max_embed = std::max(p.max_embed, ne * E);
@@ -221,10 +233,10 @@ Plan make_plan_matrix(const Spec& s) {
         GatherJob gj{};
         gj.emb_off = R.emb_off;
         gj.lib_off = lib_off[(size_t)il * s.r + ri];
-        gj.order_off = a * N;
+        gj.order_off = ord_off[a];
         gj.pts_off = R.pts_off;
         gj.pj_off = R.pj_off;
-        gj.start_off = R.slot_base;
+        gj.start_off = R.slot_base * kWaves;
         gj.l_eff = le;
         gj.n_e = ne;
         gj.n_series = N;
@@ -257,9 +269,10 @@ Plan make_plan_matrix(const Spec& s) {
   p.e_count[E] = (int)p.items.size();
   if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
   HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
-                     p.n_series, nullptr, nullptr));
-  p.device_bytes = p.n64 * 8 + p.n32 * 16 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
-                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 + p.sort_temp +
+                     p.n_sets, nullptr, nullptr));
+  p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_ord * 16 + p.n_emb * 4 + p.n_lib * 4 +
+                   p.n_pts * 4 +
+                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
                    p.n_slots * M * multi_sums_bytes() + p.n_out * 8 +
                    p.rz.size() * (sizeof(Realization) + 4) + p.items.size() * sizeof(Item) +
                    p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);

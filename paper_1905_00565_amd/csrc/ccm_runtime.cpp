@@ -72,14 +72,16 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
     upload(ex->d_plain_items, pi);
   }
   upload(ex->d_segoff, p.seg_off);
+  upload(ex->d_orders, p.orders);
   ex->d_s64.ensure(p.n64 * 8);
   ex->d_s32.ensure(p.n32 * 4);
-  ex->d_iota.ensure(p.n32 * 4);
-  ex->d_keys_out.ensure(p.n32 * 4);
-  ex->d_order.ensure(p.n32 * 4);
+  ex->d_iota.ensure(p.n_ord * 4);
+  ex->d_keys.ensure(p.n_ord * 4);
+  ex->d_keys_out.ensure(p.n_ord * 4);
+  ex->d_order.ensure(p.n_ord * 4);
   ex->d_sort_temp.ensure(p.sort_temp);
   ex->d_qord.ensure(p.n_qord * 4);
-  ex->d_start.ensure(p.n_slots * 4);
+  ex->d_start.ensure(p.n_slots * 4 * kWaves);
   ex->d_emb.ensure(p.n_emb * 4);
   ex->d_lib.ensure(p.n_lib * 4);
   ex->d_pts.ensure(p.n_pts * 4);
@@ -109,12 +111,15 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                        ex->d_s64.as<double>(), ex->d_s32.as<float>(), st));
   HIPCHK(launch_embed(ex->d_embed.as<EmbedJob>(), (int)p.embed.size(), p.max_embed,
                       ex->d_s32.as<float>(), ex->d_emb.as<float>(), st));
-  HIPCHK(launch_iota_segments(ex->d_iota.as<int32_t>(), p.spec.N, p.n_series, st));
+  HIPCHK(launch_order_keys(ex->d_orders.as<OrderJob>(), p.n_sets, ex->d_s32.as<float>(),
+                           ex->d_keys.as<uint32_t>(), st));
+  HIPCHK(launch_iota_segments(ex->d_iota.as<int32_t>(), p.spec.N, p.n_sets, st));
   {
     size_t tb = p.sort_temp;
-    HIPCHK(sort_series(ex->d_sort_temp.p, tb, ex->d_s32.as<float>(), ex->d_keys_out.as<float>(),
-                       ex->d_iota.as<int32_t>(), ex->d_order.as<int32_t>(), p.spec.N,
-                       p.n_series, ex->d_segoff.as<int32_t>(), st));
+    HIPCHK(sort_series(ex->d_sort_temp.p, tb, ex->d_keys.as<uint32_t>(),
+                       ex->d_keys_out.as<uint32_t>(), ex->d_iota.as<int32_t>(),
+                       ex->d_order.as<int32_t>(), p.spec.N, p.n_sets,
+                       ex->d_segoff.as<int32_t>(), st));
   }
   HIPCHK(launch_query_order(ex->d_embed.as<EmbedJob>(), (int)p.embed.size(),
                             ex->d_order.as<int32_t>(), ex->d_qord.as<int32_t>(), st));
@@ -465,9 +470,10 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     const int32_t sorted = ne <= gather_max_sorted_n_e() ? 1 : 0;
 
     DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_pj, d_rz, d_items, d_ingest, d_embed,
-        d_gather, d_partial, d_out, d_nbr, d_d2, d_pred, d_iota, d_keys_out, d_order,
-        d_segoff, d_temp, d_qord, d_start;
+        d_gather, d_partial, d_out, d_nbr, d_d2, d_pred, d_iota, d_keys, d_keys_out, d_order,
+        d_segoff, d_temp, d_qord, d_start, d_orders;
     std::vector<int32_t> seg{0, (int32_t)N};
+    std::vector<OrderJob> oj{{0, 0, N, E == 1 ? 0 : tau, 0}};
     size_t temp_bytes = 0;
     HIPCHK(sort_series(nullptr, temp_bytes, nullptr, nullptr, nullptr, nullptr, N, 1,
                        nullptr, nullptr));
@@ -495,6 +501,7 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     std::vector<Item> items;
     for (int t = 0; t < n_tiles; ++t) items.push_back({0, t});
     upload(d_segoff, seg);
+    upload(d_orders, oj);
     upload(d_ingest, ij);
     upload(d_embed, ej);
     upload(d_gather, gj);
@@ -503,11 +510,12 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     d_s64.ensure(2 * N * 8);
     d_s32.ensure(N * 4);
     d_iota.ensure(N * 4);
+    d_keys.ensure(N * 4);
     d_keys_out.ensure(N * 4);
     d_order.ensure(N * 4);
     d_temp.ensure(temp_bytes);
     d_qord.ensure(ne * 4);
-    d_start.ensure(n_tiles * 4);
+    d_start.ensure(n_tiles * 4 * kWaves);
     d_emb.ensure(ne * E * 4);
     d_lib.ensure(L_eff * 4);
     d_pts.ensure(L_eff * E * 4);
@@ -526,8 +534,10 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
                          d_s32.as<float>(), st));
     HIPCHK(launch_embed(d_embed.as<EmbedJob>(), 1, ne * E, d_s32.as<float>(),
                         d_emb.as<float>(), st));
+    HIPCHK(launch_order_keys(d_orders.as<OrderJob>(), 1, d_s32.as<float>(),
+                             d_keys.as<uint32_t>(), st));
     HIPCHK(launch_iota_segments(d_iota.as<int32_t>(), N, 1, st));
-    HIPCHK(sort_series(d_temp.p, temp_bytes, d_s32.as<float>(), d_keys_out.as<float>(),
+    HIPCHK(sort_series(d_temp.p, temp_bytes, d_keys.as<uint32_t>(), d_keys_out.as<uint32_t>(),
                        d_iota.as<int32_t>(), d_order.as<int32_t>(), N, 1,
                        d_segoff.as<int32_t>(), st));
     HIPCHK(launch_query_order(d_embed.as<EmbedJob>(), 1, d_order.as<int32_t>(),

@@ -76,8 +76,8 @@ enum JobState { kPending, kActive, kDone, kCancelled, kFailed };
 
 // Byte layout of one job's region in the arena.
 struct Layout {
-  uint64_t s64, s32, iota, keys, order, temp, qord, emb, lib, pts, pj, out;
-  uint64_t d_ingest, d_embed, d_sample, d_gather, d_segoff;
+  uint64_t s64, s32, iota, keys, keys_out, order, temp, qord, emb, lib, pts, pj, out;
+  uint64_t d_ingest, d_embed, d_sample, d_gather, d_segoff, d_orders;
   uint64_t bytes;
 };
 
@@ -93,9 +93,10 @@ Layout layout_of(const Plan& p) {
   };
   l.s64 = take(p.n64 * 8);
   l.s32 = take(p.n32 * 4);
-  l.iota = take(p.n32 * 4);
-  l.keys = take(p.n32 * 4);
-  l.order = take(p.n32 * 4);
+  l.iota = take(p.n_ord * 4);
+  l.keys = take(p.n_ord * 4);
+  l.keys_out = take(p.n_ord * 4);
+  l.order = take(p.n_ord * 4);
   l.temp = take(p.sort_temp);
   l.qord = take(p.n_qord * 4);
   l.emb = take(p.n_emb * 4);
@@ -108,6 +109,7 @@ Layout layout_of(const Plan& p) {
   l.d_sample = take(p.sample.size() * sizeof(SampleJob));
   l.d_gather = take(p.gather.size() * sizeof(GatherJob));
   l.d_segoff = take(p.seg_off.size() * 4);
+  l.d_orders = take(p.orders.size() * sizeof(OrderJob));
   l.bytes = o;
   return l;
 }
@@ -220,7 +222,7 @@ void start_job(ccm_server* s, Job& j) {
   const int64_t N = p.spec.N;
   // the gather writes scan starts into the server-wide slot space
   std::vector<GatherJob> gj = p.gather;
-  for (auto& g : gj) g.start_off += (int64_t)j.slot0;
+  for (auto& g : gj) g.start_off += (int64_t)j.slot0 * kWaves;
   // realizations rebased to arena-wide offsets
   std::vector<Realization> rz = p.rz;
   for (auto& R : rz) {
@@ -243,6 +245,8 @@ void start_job(ccm_server* s, Job& j) {
                    hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_segoff), p.seg_off.data(), p.seg_off.size() * 4,
                    hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_orders), p.orders.data(),
+                   p.orders.size() * sizeof(OrderJob), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(s->rz_table.as<Realization>() + j.rz0, rz.data(),
                    rz.size() * sizeof(Realization), hipMemcpyHostToDevice));
   j.X.clear();
@@ -254,11 +258,13 @@ void start_job(ccm_server* s, Job& j) {
                        at<double>(s, R0 + L.s64), at<float>(s, R0 + L.s32), st));
   HIPCHK(launch_embed(at<EmbedJob>(s, R0 + L.d_embed), (int)p.embed.size(), p.max_embed,
                       at<float>(s, R0 + L.s32), at<float>(s, R0 + L.emb), st));
-  HIPCHK(launch_iota_segments(at<int32_t>(s, R0 + L.iota), N, p.n_series, st));
+  HIPCHK(launch_order_keys(at<OrderJob>(s, R0 + L.d_orders), p.n_sets,
+                           at<float>(s, R0 + L.s32), at<uint32_t>(s, R0 + L.keys), st));
+  HIPCHK(launch_iota_segments(at<int32_t>(s, R0 + L.iota), N, p.n_sets, st));
   size_t tb = p.sort_temp;
-  HIPCHK(sort_series(at<void>(s, R0 + L.temp), tb, at<float>(s, R0 + L.s32),
-                     at<float>(s, R0 + L.keys), at<int32_t>(s, R0 + L.iota),
-                     at<int32_t>(s, R0 + L.order), N, p.n_series,
+  HIPCHK(sort_series(at<void>(s, R0 + L.temp), tb, at<uint32_t>(s, R0 + L.keys),
+                     at<uint32_t>(s, R0 + L.keys_out), at<int32_t>(s, R0 + L.iota),
+                     at<int32_t>(s, R0 + L.order), N, p.n_sets,
                      at<int32_t>(s, R0 + L.d_segoff), st));
   HIPCHK(launch_query_order(at<EmbedJob>(s, R0 + L.d_embed), (int)p.embed.size(),
                             at<int32_t>(s, R0 + L.order), at<int32_t>(s, R0 + L.qord), st));
@@ -484,7 +490,7 @@ ccm_status ccm_server_create(ccm_ctx* c, const ccm_server_cfg* cfg, ccm_server**
     s->arena_alloc.reset(budget);
     const uint64_t slots = std::max<uint64_t>(1 << 20, budget / 2048);
     s->slots_partial.ensure(slots * sizeof(Moments));
-    s->slots_start.ensure(slots * 4);
+    s->slots_start.ensure(slots * 4 * kWaves);
     s->slot_alloc.reset(slots);
     const uint64_t rzc = std::max<uint64_t>(1 << 18, budget / 8192);
     s->rz_table.ensure(rzc * sizeof(Realization));

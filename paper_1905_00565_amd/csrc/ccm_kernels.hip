@@ -434,11 +434,16 @@ struct Chunk {
 template <int E, int G>
 __device__ __forceinline__ void load_chunk(Chunk<E, G>& ch, const float* __restrict__ pts,
                                            const int32_t* __restrict__ pj, int c) {
+  // one base address per chunk: the G*E coordinates and G indices are
+  // contiguous, so the loads merge into a few wide scalar loads with
+  // immediate offsets
+  const float* __restrict__ p = pts + (int64_t)c * E;
+  const int32_t* __restrict__ q = pj + c;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) ch.p[g][k] = pts[(int64_t)(c + g) * E + k];
-    ch.j[g] = pj[c + g];
+    for (int k = 0; k < E; ++k) ch.p[g][k] = p[g * E + k];
+    ch.j[g] = q[g];
   }
 }
 

@@ -780,6 +780,24 @@ __device__ __forceinline__ void crossmap_multi_item(
 // With next == nullptr each workgroup takes items blockIdx.x, +gridDim.x, ...;
 // otherwise workgroups pull the next item from an atomic counter that starts
 // at zero (a persistent grid).
+// Workgroups are dispatched to the chip's 8 XCDs round-robin (workgroup b
+// runs on XCD b mod 8), and each XCD has an L2 of its own.  The items of one
+// realization are consecutive and all read its library, so each XCD takes
+// runs of kXcdRun consecutive items: within every group of 8*kXcdRun
+// workgroups, workgroup b takes item  group + (b mod 8)*kXcdRun + (b/8) mod
+// kXcdRun.  Workgroups past the last whole group keep their own index; the
+// map is a permutation of [0, grid), so the item set is unchanged.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 16;
+__device__ __forceinline__ int xcd_item(int b, int grid) {
+  constexpr int span = kXcds * kXcdRun;
+  const int full = grid / span * span;
+  if (b >= full) return b;
+  const int base = b / span * span;
+  const int r = b - base;
+  return base + (r % kXcds) * kXcdRun + r / kXcds;
+}
+
 template <int E, int Q, int MODE, bool DUMP>
 __global__ __launch_bounds__(kBlock) void k_crossmap(
     const Realization* __restrict__ rzs, const Item* __restrict__ items,
@@ -790,7 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_crossmap(
     int query_set, int window, Dump dump) {
   __shared__ Moments red[kBlock];
   __shared__ int s_next;
-  int it = blockIdx.x;
+  int it = xcd_item(blockIdx.x, gridDim.x);
   while (it < n_items) {
     const Item I = items[it];
     const Realization R = rzs[I.rz];
@@ -821,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_crossmap_multi(
     int window) {
   __shared__ Sums red[kBlock / 64];
   __shared__ int s_next;
-  int it = blockIdx.x;
+  int it = xcd_item(blockIdx.x, gridDim.x);
   while (it < n_items) {
     const Item I = items[it];
     const Realization R = rzs[I.rz];

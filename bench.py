@@ -11,13 +11,18 @@ The series are resident in device memory before the timed region starts.
 
 Prints one JSON line: value = cross-map predictions per second, plus
 rho-realizations per second, the roofline of the cross-map kernel (binary32
-flops per pair 3E-1, over the summed HIP-event duration of its launches), the
-served form's p50/p99 job latency on a Poisson job stream (`served`), and the
-CPU oracle timed on a bounded random sample of the same realizations.
+flops per pair 3E-1, over the summed HIP-event duration of its launches; HBM
+traffic from the committed counter summary when it matches the kernel
+sources), the other workloads of the method (`workloads`: small coupled map
+with plain vs batched launches, long noisy series, 64-series causal matrix),
+the run-time elasticity study (`elasticity`), the served form's p50/p99 job
+latency on a Poisson job stream (`served`), and the CPU oracle timed on a
+bounded random sample of the same realizations.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +37,37 @@ from paper_1905_00565_amd import capi, synth  # noqa: E402
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 
+# HBM bytes per cross-map launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# of this bench (scaled by a plain copy of known size); valid only for the
+# kernel sources it was measured on, which the file records by hash.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "crossmap_sweep_coupled_logistic_N10000_traffic.json")
+KERNEL_SOURCES = ["paper_1905_00565_amd/csrc/ccm_kernels.hip",
+                  "paper_1905_00565_amd/csrc/ccm_internal.h",
+                  "paper_1905_00565_amd/csrc/ccm_tune.h"]
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name: str):
+    """Counter-measured HBM bytes per launch, or None when the counters were
+    taken on other kernel sources or another workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    if d.get("workload") != workload_name:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -43,6 +79,9 @@ def parse():
     ap.add_argument("--flags", type=int, default=0, help="CCM_FLAG_* bits")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample (0: skip)")
+    ap.add_argument("--workloads", type=int, default=1,
+                    help="1: also time the small, long-series and causal-matrix "
+                         "workloads and the elasticity study (0: skip)")
     ap.add_argument("--serve-jobs", type=int, default=32,
                     help="jobs in the served leg (0: skip it)")
     ap.add_argument("--serve-load", type=float, default=0.7,
@@ -88,6 +127,118 @@ def cpu_baseline(w, budget_s):
             "sample": f"{done} realizations drawn uniformly at random (seed 12345) from "
                       f"the {len(grid) * w.r * 2} of the workload, {el:.1f} s on "
                       f"{threads} threads"}
+
+
+def _timed(ctx, torch, fn, reps, profile):
+    """Mean wall time per call of fn (after one untimed call), and the
+    library's kernel counters over the timed calls when profiling."""
+    ctx.profile_enable(profile)
+    fn()
+    torch.cuda.synchronize()
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    p = ctx.profile_read(reset=True)
+    if profile:
+        for k in ("kernel_ms", "launches", "pairs", "flops", "predictions", "realizations"):
+            p[k] = p[k] / reps
+    return el, p
+
+
+def _leg(ctx, torch, name, fn, reps, plain_fn=None, plain_reps=1, plain_note=None):
+    """Wall time of the batched form (graph path, no profiling), one profiled
+    pass for kernel throughput, and optionally the plain per-realization form."""
+    el, _ = _timed(ctx, torch, fn, reps, False)
+    _, p = _timed(ctx, torch, fn, 1, True)
+    out = {"workload": name, "ms_per_call": el * 1e3,
+           "predictions_per_sec": p["predictions"] / el,
+           "rho_realizations_per_sec": p["realizations"] / el,
+           "kernel_ms": p["kernel_ms"], "kernel_tflops": p["flops"] / p["kernel_ms"] / 1e9,
+           "kernel_frac_of_fp32_peak": p["flops"] / p["kernel_ms"] / 1e9 / FP32_VECTOR_PEAK_TFLOPS,
+           "pairs": p["pairs"]}
+    if plain_fn is not None:
+        b, _ = _timed(ctx, torch, plain_fn[0], plain_reps, False)
+        pl, _ = _timed(ctx, torch, plain_fn[1], plain_reps, False)
+        out["plain_vs_batched"] = {"subset": plain_note, "batched_ms": b * 1e3,
+                                   "plain_ms": pl * 1e3, "plain_over_batched": pl / b}
+    return out
+
+
+def workloads_leg(ctx, torch, dev, stream):
+    """The other configurations of the method on one GPU: the small coupled
+    map (launch-bound), the long noisy series, and the 64-series causal
+    matrix (one neighbour search per library series shared by its 63
+    targets), each with the plain per-realization form beside the batched
+    one (the matrix on its r = 1 subset)."""
+    res = {}
+    f64 = dict(dtype=torch.float64, device=dev)
+
+    w = synth.workload_small()
+    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+    a, b = torch.empty((len(w.L), w.r), **f64), torch.empty((len(w.L), w.r), **f64)
+
+    def small(flags=0):
+        return lambda: ctx.ccm_dev(X, Y, w.E[0], w.tau[0], w.L, w.r, w.seed, a, b,
+                                   stream=stream, flags=flags)
+    res["small"] = _leg(ctx, torch, w.name, small(), 20,
+                        (small(), small(capi.CCM_FLAG_PLAIN)), 3, "the whole workload")
+
+    w = synth.workload_long()
+    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+    a, b = torch.empty((len(w.L), w.r), **f64), torch.empty((len(w.L), w.r), **f64)
+    res["long"] = _leg(ctx, torch, w.name,
+                       lambda: ctx.ccm_dev(X, Y, w.E[0], w.tau[0], w.L, w.r, w.seed, a, b,
+                                           stream=stream), 1)
+
+    m = synth.workload_matrix()
+    S = torch.tensor(m["S"], device=dev)
+    M = S.shape[0]
+    rho = torch.empty((M, M, len(m["L"]), m["r"]), **f64)
+    rho1 = torch.empty((M, M, len(m["L"]), 1), **f64)
+
+    def matrix(r, out, flags=0):
+        return lambda: ctx.ccm_matrix_dev(S, m["E"], m["tau"], m["L"], r, m["seed"], out,
+                                          stream=stream, flags=flags)
+    res["matrix"] = _leg(ctx, torch, m["name"], matrix(m["r"], rho), 1,
+                         (matrix(1, rho1), matrix(1, rho1, capi.CCM_FLAG_PLAIN)), 1,
+                         "r = 1 (640 neighbour searches, 40 320 rho values)")
+    return res
+
+
+def elasticity_leg(ctx, torch, dev, stream, reps=3):
+    """Run time as one parameter doubles, after the paper's parameter study
+    (Section 4.2, Table 2): N = 4000, r = 500; each case fixes the varied
+    parameter (L in 500, 1000, 2000; E or tau in 1, 2, 4) and keeps the
+    baseline's lists for the other two.  Timed for both query sets: every
+    embedded point (cost linear in L) and the library points only (cost
+    quadratic in L, the shape of the paper's single-threaded timings)."""
+    x, y = synth.coupled_logistic(4000)
+    X, Y = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    base = {"L": [500, 1000, 2000], "E": [1, 2, 4], "tau": [1, 2, 4]}
+    out = {"workload": "coupled-logistic N=4000 r=500, baseline L=500,1000,2000 E=1,2,4 "
+                       "tau=1,2,4", "seconds": {}, "ratio_per_doubling": {}}
+    for qs in (0, 1):
+        key = "all_points" if qs == 0 else "library_points"
+        secs = {}
+        for par in ("L", "E", "tau"):
+            secs[par] = []
+            for v in base[par]:
+                g = dict(base)
+                g[par] = [v]
+                rho = torch.empty((2, len(g["E"]), len(g["tau"]), len(g["L"]), 500),
+                                  dtype=torch.float64, device=dev)
+                fn = (lambda g=g, rho=rho: ctx.ccm_sweep_dev(X, Y, g["E"], g["tau"], g["L"], 500,
+                                                             7, rho, stream=stream,
+                                                             query_set=qs))
+                el, _ = _timed(ctx, torch, fn, reps, False)
+                secs[par].append(el)
+        out["seconds"][key] = secs
+        out["ratio_per_doubling"][key] = {
+            par: [secs[par][1] / secs[par][0], secs[par][2] / secs[par][1]] for par in secs}
+    return out
 
 
 def served_leg(ctx, n_jobs, load, seed=4):
@@ -239,13 +390,17 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(w.name),
             "launches_per_step": launches / a.steps,
             "avg_launch_ms": prof["kernel_ms"] / launches,
             "kernel_share_of_step": kernel_s / el,
             "pairs_per_step": prof["pairs"] / a.steps,
         },
     }
+    if a.workloads:
+        print("bench: other workloads and the elasticity study", file=sys.stderr, flush=True)
+        out["workloads"] = workloads_leg(ctx, torch, dev, stream)
+        out["elasticity"] = elasticity_leg(ctx, torch, dev, stream)
     if a.serve_jobs > 0:
         print(f"bench: served leg, {a.serve_jobs} jobs", file=sys.stderr, flush=True)
         ctx.profile_enable(False)

@@ -18,6 +18,7 @@ struct Exec {
   DevBuf d_s64, d_s32, d_emb, d_lib, d_pts, d_pj, d_partial, d_out, d_counter;
   DevBuf d_iota, d_keys, d_keys_out, d_order, d_segoff, d_sort_temp, d_qord, d_start, d_self;
   DevBuf d_orders;
+  DevBuf d_tt;       // causal matrix: targets time-major [N][target_stride(M)]
   std::vector<int64_t> plain_first;   // per realization: first plain item
   hipGraphExec_t graph = nullptr;
   ~Exec() {

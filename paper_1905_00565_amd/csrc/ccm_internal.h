@@ -153,12 +153,18 @@ hipError_t launch_finalize(const Realization* rzs, int64_t n_rz,
 // Causal-matrix form: one neighbour search per realization predicts every
 // series; self_of[rz] is the searched series (its own target is skipped).
 // partial holds one record of multi_sums_bytes() per (item slot, series).
+// Targets come time-major: tt[t * mp + b] = series b at time t, with
+// mp = target_stride(m_series) columns (a zero pad column when m is odd).
 hipError_t launch_crossmap_multi(int E, int mode, int grid, const Realization* rzs,
                                  const int32_t* self_of, const Item* items, int n_items,
                                  int* next, const float* emb, const float* pts,
                                  const int32_t* pj, const int32_t* qord, const int32_t* start,
-                                 const double* tgt, int64_t n_series, int m_series,
+                                 const double* tt, int m_series,
                                  void* partial, int query_set, int window, hipStream_t st);
+constexpr int target_stride(int m_series) { return (m_series + 1) & ~1; }
+// tt[t * mp + b] = s64[b * n + t] for b < m, 0 in the pad column.
+hipError_t launch_transpose_targets(const double* s64, int m_series, int64_t n, double* tt,
+                                    hipStream_t st);
 hipError_t launch_finalize_multi(const Realization* rzs, const int32_t* self_of,
                                  int64_t n_rz, int m_series, const void* partial,
                                  int64_t out_stride_b, double* out, hipStream_t st);

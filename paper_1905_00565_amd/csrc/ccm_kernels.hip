@@ -703,17 +703,60 @@ __device__ __forceinline__ void sums_merge(Sums& a, const Sums& b) {
   a.v[9] = fmax(a.v[9], b.v[9]);
 }
 
+__device__ __forceinline__ void sums_init(Sums& su) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) su.v[i] = 0.0;
+  su.v[6] = su.v[8] = __builtin_inf();
+  su.v[7] = su.v[9] = -__builtin_inf();
+}
+
+__device__ __forceinline__ void sums_add(Sums& su, double o, double pred, double shift) {
+  const double a = o - shift, p = pred - shift;
+  su.v[0] += 1.0;
+  su.v[1] += a;
+  su.v[2] += p;
+  su.v[3] += a * a;
+  su.v[4] += p * p;
+  su.v[5] += a * p;
+  su.v[6] = fmin(su.v[6], o);
+  su.v[7] = fmax(su.v[7], o);
+  su.v[8] = fmin(su.v[8], pred);
+  su.v[9] = fmax(su.v[9], pred);
+}
+
+// Order a wavefront's LDS accesses (its lanes read what other lanes wrote).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS of the many-target item: per wavefront, one query set's neighbours
+// (w double [K][64], row offsets nj*mp int32 [K][64], qi*mp int32 [64]);
+// reused afterwards for the wavefronts' per-target sums (Sums [kWaves][64]).
+// A row offset fits in int32: it is below N*mp <= M*N + N, and the planner
+// caps M*N at INT32_MAX/2.
+template <int E>
+struct MultiLds {
+  static constexpr int K = E + 1;
+  static constexpr int kWave = 64 * (K * 12 + 4);
+  static constexpr int kStage = kWaves * kWave;
+  static constexpr int kRed = kWaves * 64 * (int)sizeof(Sums);
+  static constexpr int kBytes = kStage > kRed ? kStage : kRed;
+};
+
 template <int E, int Q, int MODE>
 __device__ __forceinline__ void crossmap_multi_item(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
     const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tgt_pool, int64_t n_series, int m_series, int self,
-    Sums* __restrict__ partial, int query_set, int window, Sums* red) {
+    const double* __restrict__ tt, int m_series, int self,
+    Sums* __restrict__ partial, int query_set, int window, unsigned char* lds) {
   constexpr int K = E + 1;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int mp = target_stride(m_series);
   const int64_t off = (int64_t)(E - 1) * R.tau;
 
   ScanState<E, Q, MODE> S;
@@ -729,48 +772,77 @@ __device__ __forceinline__ void crossmap_multi_item(
     simplex_weights<K>(nd, w[m]);
   }
 
-  for (int bt = 0; bt < m_series; ++bt) {
-    if (bt == self) continue;
-    const double* __restrict__ T = tgt_pool + (int64_t)bt * n_series + off;
-    const double shift = T[0];
+  // Per-target stage.  Row t of the time-major table holds every series'
+  // value at time t.  Lane b of a wavefront owns target b0 + b and walks the
+  // wavefront's queries (staged in LDS one query set at a time): each
+  // neighbour's row is then read by one coalesced load for all 64 targets.
+  // A target's sums are shifted by its first embedded value (time off).
+  unsigned char* stage = lds + wave * MultiLds<E>::kWave;
+  double* __restrict__ sw = reinterpret_cast<double*>(stage);
+  int32_t* __restrict__ srow = reinterpret_cast<int32_t*>(stage + 64 * K * 8);
+  int32_t* __restrict__ sqrow = reinterpret_cast<int32_t*>(stage + 64 * K * 12);
+  Sums* __restrict__ red = reinterpret_cast<Sums*>(lds);
+  const double* __restrict__ T = tt + off * mp;
+  for (int b0 = 0; b0 < m_series; b0 += 64) {
+    const int b = b0 + lane;
+    const bool act = b < m_series;
+    const double* __restrict__ Tb = T + (act ? b : 0);
+    const double shift = Tb[0];
     Sums su;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) su.v[i] = 0.0;
-    su.v[6] = su.v[8] = __builtin_inf();
-    su.v[7] = su.v[9] = -__builtin_inf();
+    sums_init(su);
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
-      if (S.qi[m] < 0) continue;
-      double pred = 0.0;
+      // valid queries are a prefix of the lanes (the tail of the last tile
+      // is invalid)
+      const int nq = __popcll(__builtin_amdgcn_ballot_w64(S.qi[m] >= 0));
+      sqrow[lane] = S.qi[m] * mp;
 #pragma unroll
-      for (int t = 0; t < K; ++t) pred += w[m][t] * T[nj[m][t]];
-      const double o = T[S.qi[m]];
-      const double a = o - shift, p = pred - shift;
-      su.v[0] += 1.0;
-      su.v[1] += a;
-      su.v[2] += p;
-      su.v[3] += a * a;
-      su.v[4] += p * p;
-      su.v[5] += a * p;
-      su.v[6] = fmin(su.v[6], o);
-      su.v[7] = fmax(su.v[7], o);
-      su.v[8] = fmin(su.v[8], pred);
-      su.v[9] = fmax(su.v[9], pred);
+      for (int t = 0; t < K; ++t) {
+        srow[t * 64 + lane] = nj[m][t] * mp;
+        sw[t * 64 + lane] = w[m][t];
+      }
+      wave_sync();
+      if (act) {
+        // two queries per step, every load issued before any is used
+        int q = 0;
+        for (; q + 2 <= nq; q += 2) {
+          double v[2][K], o[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int t = 0; t < K; ++t) v[u][t] = Tb[srow[t * 64 + q + u]];
+            o[u] = Tb[sqrow[q + u]];
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            double pred = 0.0;
+#pragma unroll
+            for (int t = 0; t < K; ++t) pred += sw[t * 64 + q + u] * v[u][t];
+            sums_add(su, o[u], pred, shift);
+          }
+        }
+        if (q < nq) {
+          double v[K];
+#pragma unroll
+          for (int t = 0; t < K; ++t) v[t] = Tb[srow[t * 64 + q]];
+          const double o = Tb[sqrow[q]];
+          double pred = 0.0;
+#pragma unroll
+          for (int t = 0; t < K; ++t) pred += sw[t * 64 + q] * v[t];
+          sums_add(su, o, pred, shift);
+        }
+      }
+      wave_sync();
     }
-#pragma unroll
-    for (int sh = 32; sh >= 1; sh >>= 1) {
-      Sums o;
-#pragma unroll
-      for (int i = 0; i < 10; ++i) o.v[i] = __shfl_xor(su.v[i], sh, 64);
-      sums_merge(su, o);
-    }
-    if (lane == 0) red[wave] = su;
+    // wavefronts' sums -> LDS (over the staging area), merged in order
     __syncthreads();
-    if (tid == 0) {
-      Sums tot = red[0];
+    red[wave * 64 + lane] = su;
+    __syncthreads();
+    if (wave == 0 && act && b != self) {
+      Sums tot = red[lane];
 #pragma unroll
-      for (int wv = 1; wv < kBlock / 64; ++wv) sums_merge(tot, red[wv]);
-      partial[(R.slot_base + tile) * m_series + bt] = tot;
+      for (int wv = 1; wv < kWaves; ++wv) sums_merge(tot, red[wv * 64 + lane]);
+      partial[(R.slot_base + tile) * m_series + b] = tot;
     }
     __syncthreads();
   }
@@ -834,18 +906,17 @@ __global__ __launch_bounds__(kBlock) void k_crossmap_multi(
     const Item* __restrict__ items, int n_items, int* __restrict__ next,
     const float* __restrict__ emb_pool, const float* __restrict__ pts_pool,
     const int32_t* __restrict__ pj_pool, const int32_t* __restrict__ qord_pool,
-    const int32_t* __restrict__ start_pool, const double* __restrict__ tgt_pool,
-    int64_t n_series, int m_series, Sums* __restrict__ partial, int query_set,
-    int window) {
-  __shared__ Sums red[kBlock / 64];
+    const int32_t* __restrict__ start_pool, const double* __restrict__ tt,
+    int m_series, Sums* __restrict__ partial, int query_set, int window) {
+  __shared__ __align__(16) unsigned char lds[MultiLds<E>::kBytes];
   __shared__ int s_next;
   int it = xcd_item(blockIdx.x, gridDim.x);
   while (it < n_items) {
     const Item I = items[it];
     const Realization R = rzs[I.rz];
     crossmap_multi_item<E, Q, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool,
-                                    start_pool, tgt_pool, n_series, m_series,
-                                    self_of[I.rz], partial, query_set, window, red);
+                                    start_pool, tt, m_series, self_of[I.rz], partial,
+                                    query_set, window, lds);
     if (next == nullptr) {
       it += gridDim.x;
     } else {
@@ -1063,26 +1134,43 @@ static hipError_t launch_multi_e(int mode, int grid, const Realization* rzs,
                                  const int32_t* self_of, const Item* items, int n_items,
                                  int* next, const float* emb, const float* pts,
                                  const int32_t* pj, const int32_t* qord, const int32_t* start,
-                                 const double* tgt, int64_t n_series, int m_series,
+                                 const double* tt, int m_series,
                                  Sums* partial, int query_set, int window, hipStream_t st) {
   constexpr int Q = DefaultQ<E>::Q;
   switch (mode) {
     case kExclSelf:
       k_crossmap_multi<E, Q, kExclSelf><<<grid, kBlock, 0, st>>>(
-          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tgt, n_series,
-          m_series, partial, query_set, window);
+          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
+          partial, query_set, window);
       break;
     case kKeepSelf:
       k_crossmap_multi<E, Q, kKeepSelf><<<grid, kBlock, 0, st>>>(
-          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tgt, n_series,
-          m_series, partial, query_set, window);
+          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
+          partial, query_set, window);
       break;
     default:
       k_crossmap_multi<E, Q, kWindow><<<grid, kBlock, 0, st>>>(
-          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tgt, n_series,
-          m_series, partial, query_set, window);
+          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
+          partial, query_set, window);
       break;
   }
+  return hipGetLastError();
+}
+
+__global__ void k_transpose_targets(const double* __restrict__ s64, int m, int mp, int64_t n,
+                                    double* __restrict__ tt) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n * mp;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = x / mp;
+    const int b = (int)(x - t * mp);
+    tt[x] = b < m ? s64[(int64_t)b * n + t] : 0.0;
+  }
+}
+
+hipError_t launch_transpose_targets(const double* s64, int m_series, int64_t n, double* tt,
+                                    hipStream_t st) {
+  const int mp = target_stride(m_series);
+  k_transpose_targets<<<blocks_for(n * mp, 256), 256, 0, st>>>(s64, m_series, mp, n, tt);
   return hipGetLastError();
 }
 
@@ -1090,7 +1178,7 @@ hipError_t launch_crossmap_multi(int E, int mode, int grid, const Realization* r
                                  const int32_t* self_of, const Item* items, int n_items,
                                  int* next, const float* emb, const float* pts,
                                  const int32_t* pj, const int32_t* qord, const int32_t* start,
-                                 const double* tgt, int64_t n_series, int m_series,
+                                 const double* tt, int m_series,
                                  void* partial, int query_set, int window, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   Sums* ps = static_cast<Sums*>(partial);
@@ -1098,7 +1186,7 @@ hipError_t launch_crossmap_multi(int E, int mode, int grid, const Realization* r
 #define CCM_MCASE(e)                                                                     \
   case e:                                                                                \
     return launch_multi_e<e>(mode, grid, rzs, self_of, items, n_items, next, emb, pts, pj, \
-                             qord, start, tgt, n_series, m_series, ps, query_set, window, st);
+                             qord, start, tt, m_series, ps, query_set, window, st);
     CCM_MCASE(1) CCM_MCASE(2) CCM_MCASE(3) CCM_MCASE(4) CCM_MCASE(5)
     CCM_MCASE(6) CCM_MCASE(7) CCM_MCASE(8) CCM_MCASE(9) CCM_MCASE(10)
 #undef CCM_MCASE

@@ -274,6 +274,7 @@ Plan make_plan_matrix(const Spec& s) {
                    p.n_pts * 4 +
                    p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
                    p.n_slots * M * multi_sums_bytes() + p.n_out * 8 +
+                   N * target_stride(M) * 8 +
                    p.rz.size() * (sizeof(Realization) + 4) + p.items.size() * sizeof(Item) +
                    p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
   return p;

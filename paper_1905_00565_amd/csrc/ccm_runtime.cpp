@@ -88,6 +88,7 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
   ex->d_pj.ensure(p.n_pj * 4);
   if (s.M > 0) {
     upload(ex->d_self, p.self_of);
+    ex->d_tt.ensure((size_t)s.N * target_stride(s.M) * 8);
     ex->d_partial.ensure((size_t)p.n_slots * s.M * multi_sums_bytes());
   } else {
     ex->d_partial.ensure(p.n_slots * sizeof(Moments));
@@ -111,6 +112,9 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                        ex->d_s64.as<double>(), ex->d_s32.as<float>(), st));
   HIPCHK(launch_embed(ex->d_embed.as<EmbedJob>(), (int)p.embed.size(), p.max_embed,
                       ex->d_s32.as<float>(), ex->d_emb.as<float>(), st));
+  if (p.spec.M > 0)
+    HIPCHK(launch_transpose_targets(ex->d_s64.as<double>(), p.spec.M, p.spec.N,
+                                    ex->d_tt.as<double>(), st));
   HIPCHK(launch_order_keys(ex->d_orders.as<OrderJob>(), p.n_sets, ex->d_s32.as<float>(),
                            ex->d_keys.as<uint32_t>(), st));
   HIPCHK(launch_iota_segments(ex->d_iota.as<int32_t>(), p.spec.N, p.n_sets, st));
@@ -154,8 +158,8 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                      ex->d_items.as<Item>() + p.e_first[E], n, next,
                                      ex->d_emb.as<float>(), ex->d_pts.as<float>(),
                                      ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
-                                     ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
-                                     p.spec.N, p.spec.M, ex->d_partial.p, p.spec.query_set,
+                                     ex->d_start.as<int32_t>(), ex->d_tt.as<double>(),
+                                     p.spec.M, ex->d_partial.p, p.spec.query_set,
                                      p.window, st));
       else
         HIPCHK(launch_crossmap(E, p.mode, false, grid, ex->d_rz.as<Realization>(),
@@ -198,7 +202,7 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                      R.n_tiles, nullptr, ex->d_emb.as<float>(),
                                      ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
                                      ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
-                                     ex->d_s64.as<double>(), p.spec.N, p.spec.M,
+                                     ex->d_tt.as<double>(), p.spec.M,
                                      ex->d_partial.p, p.spec.query_set, p.window, st));
       else
         HIPCHK(launch_crossmap(R.E, p.mode, false, R.n_tiles, ex->d_rz.as<Realization>(),

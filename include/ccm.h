@@ -92,6 +92,18 @@ typedef struct {
 /* Cross-map kernel as a persistent grid pulling work items from an atomic
    queue (default: one workgroup per work item, longest first). */
 #define CCM_FLAG_PERSISTENT 4u
+/* Distance indexing table (Section 3.2): before the cross map, build for
+   every library embedding that needs it a table whose row i lists the
+   first CCM_TABLE_WIDTH embedded points in ascending (d2, index) order
+   from point i, and find each query's E+1 neighbours by walking its row
+   until E+1 library members (not excluded) are seen.  Used for the
+   realizations whose expected walk is short (large libraries); the others,
+   and any wavefront whose walk runs off the end of its rows, scan by brute
+   force.  Neighbours, predictions and rho are bitwise identical to the
+   brute-force path.  Costs n_e * CCM_TABLE_WIDTH * 4 bytes of device memory
+   per table.  Not supported by the served form (ignored there). */
+#define CCM_FLAG_TABLE 8u
+#define CCM_TABLE_WIDTH 1024
 
 /* Create a context on HIP device `device`.  *out receives the handle. */
 ccm_status ccm_create(int device, ccm_ctx **out);
@@ -250,6 +262,9 @@ ccm_status ccm_library(ccm_ctx *ctx, int64_t N_e, int32_t E, int32_t tau,
  *   d2          host float[Nq][E+1] (nullable): their squared distances
  *   pred        host double[Nq] (nullable): predictions
  *   rho         host double (nullable): the skill
+ * With CCM_FLAG_TABLE in opts->flags the realization walks a distance
+ * indexing table over the embedding whatever its size (the walk, and its
+ * fallback to the scan when a row runs short, give the same results).
  */
 ccm_status ccm_neighbors(ccm_ctx *ctx, const double *lib_series,
                          const double *target, int64_t N, int32_t E,
@@ -266,6 +281,7 @@ typedef struct {
   double flops;          /* 3E-1 binary32 flops per pair, summed */
   double predictions;    /* cross-map predictions made */
   double realizations;   /* rho values produced */
+  double table_realizations; /* of which walked a distance indexing table */
 } ccm_profile;
 
 ccm_status ccm_profile_enable(ccm_ctx *ctx, int on);

@@ -31,15 +31,19 @@ from . import build as B
 
 TUNE_DIR = os.path.join(B.PKG, "_tune")
 
-# (Q, G) candidates per E; the first is the hand-picked starting point.
+# (Q, G) candidates per E; the first is the current table's choice.
 CANDIDATES = {
-    1: [(4, 16), (4, 8), (2, 16), (4, 12)],
-    2: [(4, 8), (4, 16), (4, 4), (2, 8)],
-    3: [(4, 8), (4, 4), (2, 8), (3, 8)],
-    4: [(4, 8), (4, 4), (2, 8), (3, 8)],
+    1: [(3, 16), (4, 16), (4, 8), (4, 12), (2, 16), (4, 24)],
+    2: [(4, 8), (4, 16), (4, 12), (4, 6), (3, 8), (2, 16)],
+    3: [(4, 8), (4, 12), (4, 6), (3, 8), (4, 4), (2, 16)],
+    4: [(4, 6), (4, 8), (4, 12), (3, 8), (4, 4), (2, 12)],
+    5: [(3, 6), (3, 4), (4, 4), (2, 8), (3, 8), (4, 6)],
+    6: [(4, 6), (4, 4), (3, 6), (2, 8), (3, 4), (4, 3)],
+    7: [(4, 4), (4, 3), (3, 4), (2, 6), (3, 6), (2, 8)],
+    8: [(3, 4), (3, 3), (4, 3), (2, 6), (3, 6), (2, 4)],
+    9: [(3, 4), (3, 3), (2, 6), (3, 6), (2, 4), (4, 3)],
+    10: [(2, 3), (2, 4), (3, 3), (2, 6), (3, 4), (2, 8)],
 }
-for _e in range(5, 11):
-    CANDIDATES[_e] = [(2, 4), (4, 4), (3, 4), (2, 3), (3, 3), (4, 3)]
 
 
 def columns():

@@ -30,6 +30,8 @@ CCM_E_TIMEOUT = -6
 CCM_FLAG_PLAIN = 1
 CCM_FLAG_NO_GRAPH = 2
 CCM_FLAG_PERSISTENT = 4
+CCM_FLAG_TABLE = 8
+CCM_TABLE_WIDTH = 1024
 
 # Every symbol include/ccm.h declares (checked by the ABI test).
 EXPORTS = [
@@ -50,7 +52,8 @@ class ccm_opts(C.Structure):
 class ccm_profile(C.Structure):
     _fields_ = [("kernel_ms", C.c_double), ("launches", C.c_int64),
                 ("pairs", C.c_double), ("flops", C.c_double),
-                ("predictions", C.c_double), ("realizations", C.c_double)]
+                ("predictions", C.c_double), ("realizations", C.c_double),
+                ("table_realizations", C.c_double)]
 
 
 class ccm_server_cfg(C.Structure):
@@ -270,7 +273,7 @@ def ccm_library(ctx, N_e, E, tau, L_eff, r_index, seed):
 
 
 def ccm_neighbors(ctx, lib_series, target, E, tau, lib_idx, exclusion_radius=0,
-                  query_set=0):
+                  query_set=0, flags=0):
     """(nbr [Nq][E+1], d2 [Nq][E+1] float32, pred [Nq], rho) of one library."""
     S, T = _f64(lib_series), _f64(target)
     li = np.ascontiguousarray(lib_idx, dtype=np.int32)
@@ -281,7 +284,7 @@ def ccm_neighbors(ctx, lib_series, target, E, tau, lib_idx, exclusion_radius=0,
     d2 = np.empty((max(nq, 1), E + 1), dtype=np.float32)
     pred = np.empty(max(nq, 1), dtype=np.float64)
     rho = C.c_double()
-    o = _opts(exclusion_radius, query_set, 0)
+    o = _opts(exclusion_radius, query_set, flags)
     _check(ctx, lib().ccm_neighbors(ctx, _ptr(S), _ptr(T), N, E, tau, _ptr(li), len(li),
                                     C.byref(o), _ptr(nbr), _ptr(d2), _ptr(pred),
                                     C.byref(rho)))

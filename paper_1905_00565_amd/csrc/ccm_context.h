@@ -19,6 +19,7 @@ struct Exec {
   DevBuf d_iota, d_keys, d_keys_out, d_order, d_segoff, d_sort_temp, d_qord, d_start, d_self;
   DevBuf d_orders;
   DevBuf d_tt;       // causal matrix: targets time-major [N][target_stride(M)]
+  DevBuf d_tables, d_table;   // distance indexing table jobs and rows
   std::vector<int64_t> plain_first;   // per realization: first plain item
   hipGraphExec_t graph = nullptr;
   ~Exec() {

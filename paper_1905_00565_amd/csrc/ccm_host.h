@@ -139,7 +139,20 @@ struct Plan {
   std::vector<int64_t> L_eff;   // per (iE, itau, iL)
   double pairs = 0, flops = 0, preds = 0;
   size_t device_bytes = 0;
+  // distance indexing tables (CCM_FLAG_TABLE), grouped by E
+  std::vector<TableJob> tables;
+  int64_t n_table = 0;                // int32 entries of every table
+  int te_first[kMaxE + 1] = {0};
+  int te_count[kMaxE + 1] = {0};
+  int te_max_ne[kMaxE + 1] = {0};     // largest table of E (launch grid)
+  int e_table_ne[kMaxE + 1] = {0};    // largest n_e walked by E's items (launch LDS)
+  int64_t table_rz = 0;               // realizations that walk a table
 };
+
+// Whether a realization walks a distance indexing table, and the offset of
+// that table (created on first use for the embedding at emb_off).
+bool use_table(const Plan& p, int E, int64_t ne, int64_t le);
+int64_t table_for(Plan& p, int64_t emb_off, int64_t ne, int E);
 
 // Order set of (series, tau) -- tau 0 for the value order -- created on
 // first use; returns its offset in the order pool.

@@ -102,6 +102,22 @@ struct Realization {
   int32_t n_tiles;   // query tiles (= work items) of this realization
   int64_t slot_base; // first partial-moment slot (one per tile; scan starts kWaves per slot)
   int64_t out_index; // where rho goes in the caller's output
+  int64_t table_off; // int32: distance-index rows of the embedding, or -1 (brute force)
+  int32_t table_w;   // entries per table row (min(CCM_TABLE_WIDTH, n_e))
+  int32_t pad;
+};
+
+// One distance indexing table: for each embedded point i of one embedding,
+// row i = the first w embedded points j (self included) in ascending
+// (d2(i, j), j) order, with d2 the kernel's binary32 distance.
+struct TableJob {
+  int64_t emb_off;   // floats: AoS embedding
+  int64_t out_off;   // int32: rows [n_e][w]
+  int64_t row0;      // first global row of this table (rows are launched flat)
+  int32_t n_e;
+  int32_t E;
+  int32_t w;
+  int32_t pad;
 };
 
 // A work item: one query tile of one realization.
@@ -146,7 +162,15 @@ hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
                            const float* pts, const int32_t* pj,
                            const int32_t* qord, const int32_t* start,
                            const double* tgt, Moments* partial, int query_set,
-                           int window, Dump d, hipStream_t st);
+                           int window, Dump d, const int32_t* table, int table_n_e,
+                           hipStream_t st);
+// Distance indexing tables (Section 3.2), one launch per E: grid
+// (max_n_e, n_jobs); rows of job k at table + jobs[k].out_off.
+hipError_t launch_table_build(int E, const TableJob* jobs, int n_jobs, int max_n_e,
+                              const float* emb, int32_t* table, hipStream_t st);
+constexpr int kTableWidth = 1024;           // CCM_TABLE_WIDTH
+constexpr int kTableMaxNe = 131072;         // largest embedding given a table (LDS bitmask)
+constexpr int table_row_stride(int w) { return (w + 3) & ~3; }
 hipError_t launch_finalize(const Realization* rzs, int64_t n_rz,
                            const Moments* partial, double* out, hipStream_t st);
 
@@ -160,7 +184,8 @@ hipError_t launch_crossmap_multi(int E, int mode, int grid, const Realization* r
                                  int* next, const float* emb, const float* pts,
                                  const int32_t* pj, const int32_t* qord, const int32_t* start,
                                  const double* tt, int m_series,
-                                 void* partial, int query_set, int window, hipStream_t st);
+                                 void* partial, int query_set, int window,
+                                 const int32_t* table, int table_n_e, hipStream_t st);
 constexpr int target_stride(int m_series) { return (m_series + 1) & ~1; }
 // tt[t * mp + b] = s64[b * n + t] for b < m, 0 in the pad column.
 hipError_t launch_transpose_targets(const double* s64, int m_series, int64_t n, double* tt,

@@ -512,12 +512,94 @@ struct ScanState {
   double key[Q][Slots<E, MODE>::KS];
 };
 
+// ---------------------------------------------------------------------------
+// distance indexing table (Section 3.2)
+// ---------------------------------------------------------------------------
+//
+// The walk of a query's table row: the first E+1 library members that are
+// not excluded, in the row's (d2, j) order, are exactly the E+1 neighbours
+// the brute-force scan selects (every candidate before them in the row is
+// either outside the library or excluded, and every candidate after them is
+// larger in (d2, j)).  Their keys are recomputed from the coordinates with
+// the same binary32 chain, so the running lists end identical.  The library
+// is a membership bitmask in LDS (built per item), the accepted indices go to
+// a per-lane LDS slot array.  Returns false when some lane of the wavefront
+// reached the end of a row short of E+1 members (the caller then scans).
+
+struct TableArgs {
+  const int32_t* pool;  // int32 rows of every table
+  int32_t words;        // bitmask words in dynamic LDS (0: no table in this launch)
+  int32_t pad;
+};
+
+__device__ __forceinline__ int table_stride(int w) { return (w + 3) & ~3; }
+
+template <int E, int Q, int MODE>
+__device__ __forceinline__ bool walk_table(const Realization& R, const int32_t* __restrict__ table,
+                                           const uint32_t* __restrict__ bits,
+                                           int32_t* __restrict__ acc,
+                                           const float* __restrict__ emb, int window,
+                                           ScanState<E, Q, MODE>& S) {
+  constexpr int K = E + 1;
+  const int rs = table_stride(R.table_w);
+  bool ok = true;
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    const int qi = S.qi[m];
+    int cnt = qi >= 0 ? 0 : K;
+    if (qi >= 0) {
+      const int4* __restrict__ row =
+          reinterpret_cast<const int4*>(table + R.table_off + (int64_t)qi * rs);
+      for (int p = 0; p < rs / 4 && cnt < K; ++p) {
+        const int4 v = row[p];
+        const int js[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = js[u];
+          bool keep = cnt < K && j >= 0 && ((bits[j >> 5] >> (j & 31)) & 1u);
+          if (MODE == kExclSelf) keep = keep && j != qi;
+          if (MODE == kWindow) keep = keep && (j - qi > window || qi - j > window);
+          if (keep) {
+            acc[cnt * kBlock + threadIdx.x] = j;
+            ++cnt;
+          }
+        }
+      }
+      if (cnt == K) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const int j = acc[t * kBlock + threadIdx.x];
+          S.key[m][t] = make_key(sqdist<E>(S.qc[m], emb + (int64_t)j * E), j);
+        }
+      }
+    }
+    ok = ok && cnt == K;
+  }
+  return !__builtin_amdgcn_ballot_w64(!ok);
+}
+
+// Library membership bitmask of realization R in LDS (whole workgroup).
+__device__ __forceinline__ void table_bitmask(const Realization& R,
+                                              const int32_t* __restrict__ pj_pool,
+                                              uint32_t* bits) {
+  const int words = (R.n_e + 31) / 32;
+  for (int w = threadIdx.x; w < words; w += kBlock) bits[w] = 0u;
+  __syncthreads();
+  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
+  for (int c = threadIdx.x; c < R.l_eff; c += kBlock) {
+    const int j = pj[c];
+    atomicOr(&bits[j >> 5], 1u << (j & 31));
+  }
+  __syncthreads();
+}
+
 template <int E, int Q, int MODE>
 __device__ __forceinline__ void scan_library(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
     const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    int query_set, int window, ScanState<E, Q, MODE>& S) {
+    int query_set, int window, const TableArgs& ta, uint32_t* tlds,
+    ScanState<E, Q, MODE>& S) {
   constexpr int KS = Slots<E, MODE>::KS;
   constexpr int G = Group<E>::G;
   constexpr int QT = kBlock * Q;                    // queries per tile
@@ -553,6 +635,17 @@ __device__ __forceinline__ void scan_library(
 
   // A wavefront with no query (the tail of the last tile) has nothing to scan.
   if (!__builtin_amdgcn_ballot_w64(any)) return;
+
+  // Table walk (the realization's rows exist): done unless a row ran short.
+  if (R.table_off >= 0 && ta.words > 0) {
+    if (walk_table<E, Q, MODE>(R, ta.pool, tlds, reinterpret_cast<int32_t*>(tlds + ta.words),
+                               emb, window, S))
+      return;
+#pragma unroll
+    for (int m = 0; m < Q; ++m)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
+  }
 
   // Brute-force scan of every library position, outward from the
   // wavefront's start s0: a forward group [f, f+G) and a backward group
@@ -631,15 +724,17 @@ __device__ __forceinline__ void crossmap_item(
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
     const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
     const double* __restrict__ tgt_pool, Moments* __restrict__ partial,
-    int query_set, int window, const Dump& dump, Moments* red) {
+    int query_set, int window, const Dump& dump, Moments* red, const TableArgs& ta,
+    uint32_t* tlds) {
   constexpr int K = E + 1;                          // neighbours (Section 3.2)
   const int tid = threadIdx.x;
   const double* __restrict__ tgt = tgt_pool + R.tgt_off;
   const int64_t off = (int64_t)(E - 1) * R.tau;     // time of embedded point 0
 
+  if (R.table_off >= 0 && ta.words > 0) table_bitmask(R, pj_pool, tlds);
   ScanState<E, Q, MODE> S;
   scan_library<E, Q, MODE>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
-                           query_set, window, S);
+                           query_set, window, ta, tlds, S);
 
   // Simplex projection from the E+1 neighbours, then Pearson moments.
   Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -751,7 +846,8 @@ __device__ __forceinline__ void crossmap_multi_item(
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
     const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
     const double* __restrict__ tt, int m_series, int self,
-    Sums* __restrict__ partial, int query_set, int window, unsigned char* lds) {
+    Sums* __restrict__ partial, int query_set, int window, unsigned char* lds,
+    const TableArgs& ta, uint32_t* tlds) {
   constexpr int K = E + 1;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -759,9 +855,10 @@ __device__ __forceinline__ void crossmap_multi_item(
   const int mp = target_stride(m_series);
   const int64_t off = (int64_t)(E - 1) * R.tau;
 
+  if (R.table_off >= 0 && ta.words > 0) table_bitmask(R, pj_pool, tlds);
   ScanState<E, Q, MODE> S;
   scan_library<E, Q, MODE>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
-                           query_set, window, S);
+                           query_set, window, ta, tlds, S);
 
   double w[Q][K];
   int32_t nj[Q][K];
@@ -848,6 +945,127 @@ __device__ __forceinline__ void crossmap_multi_item(
   }
 }
 
+// Build one row of a distance indexing table (one workgroup per row i): the
+// first w points j of [0, n_e) in ascending (d2(i, j), j) order.  d2 is the
+// cross-map kernel's binary32 distance; its bit pattern orders like its value
+// (d2 >= +0), so the w-th smallest value T is found by a three-pass radix
+// select on the bits (11, 11 and 10 bits, histograms in LDS), recomputing
+// the distances on each pass.  Then every j with d2 < T is kept, plus the
+// lowest-index ones with d2 == T up to w in all, and the w keys (d2 bits,
+// j) are sorted by a bitonic network in LDS.  Row stride: w rounded up to a
+// multiple of 4, padded with -1.
+constexpr int kTableMaxW = 1024;
+
+template <int E>
+__global__ __launch_bounds__(kBlock) void k_table_build(const TableJob* __restrict__ jobs,
+                                                        const float* __restrict__ emb_pool,
+                                                        int32_t* __restrict__ table_pool) {
+  __shared__ uint32_t hist[2048];
+  __shared__ uint64_t keys[kTableMaxW];
+  __shared__ uint32_t s_sel[2];
+  __shared__ int s_wave[kBlock / 64];
+  __shared__ int s_lt;
+  const TableJob J = jobs[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= J.n_e) return;                       // uniform: whole workgroup
+  const int tid = threadIdx.x;
+  const float* __restrict__ emb = emb_pool + J.emb_off;
+  float q[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) q[k] = emb[(int64_t)i * E + k];
+  const int n = J.n_e;
+  const int w = J.w;
+
+  uint32_t prefix = 0, mask = 0;
+  uint32_t need = (uint32_t)w;                  // rank of T among the matching values
+  for (int pass = 0; pass < 3; ++pass) {
+    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+    const int nbins = pass == 2 ? 1024 : 2048;
+    for (int b = tid; b < nbins; b += kBlock) hist[b] = 0u;
+    __syncthreads();
+    for (int j = tid; j < n; j += kBlock) {
+      const uint32_t u = __float_as_uint(sqdist<E>(q, emb + (int64_t)j * E));
+      if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & (nbins - 1)], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // bin holding the need-th value: lanes own nbins/64 consecutive bins
+      const int per = nbins / 64;
+      uint32_t loc = 0;
+      for (int b = 0; b < per; ++b) loc += hist[tid * per + b];
+      uint32_t inc = loc;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (tid >= o) inc += y;
+      }
+      const uint32_t exc = inc - loc;
+      if (exc < need && need <= inc) {
+        uint32_t c = exc;
+        for (int b = 0; b < per; ++b) {
+          const uint32_t h = hist[tid * per + b];
+          if (c + h >= need) {
+            s_sel[0] = (uint32_t)(tid * per + b);
+            s_sel[1] = c;
+            break;
+          }
+          c += h;
+        }
+      }
+    }
+    __syncthreads();
+    prefix |= s_sel[0] << shift;
+    mask |= (uint32_t)(nbins - 1) << shift;
+    need -= s_sel[1];
+    __syncthreads();
+  }
+  // prefix = T (all 32 bits fixed); `need` values equal to T are taken,
+  // the w - need values below T all are.
+  const uint32_t T = prefix;
+  if (tid == 0) s_lt = 0;
+  __syncthreads();
+  int eq_seen = 0;
+  for (int base = 0; base < n; base += kBlock) {
+    const int j = base + tid;
+    const uint32_t u = j < n ? __float_as_uint(sqdist<E>(q, emb + (int64_t)min(j, n - 1) * E))
+                             : 0xffffffffu;
+    const bool lt = j < n && u < T;
+    const bool eq = j < n && u == T;
+    if (lt) {
+      const int pos = atomicAdd(&s_lt, 1);
+      if (pos < w) keys[pos] = ((uint64_t)u << 32) | (uint32_t)j;
+    }
+    int tot;
+    const int r = block_rank(eq, s_wave, tot);
+    const int pe = w - (int)need + eq_seen + r;
+    if (eq && eq_seen + r < (int)need && pe >= 0 && pe < w)
+      keys[pe] = ((uint64_t)u << 32) | (uint32_t)j;
+    eq_seen += tot;
+  }
+  // bitonic sort of keys[0..P), P = the power of two >= w, padded with ~0
+  int P = 1;
+  while (P < w) P <<= 1;
+  for (int x = w + tid; x < P; x += kBlock) keys[x] = ~0ull;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int x = tid; x < P / 2; x += kBlock) {
+        const int lo = 2 * x - (x & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t a = keys[lo], b = keys[hi];
+        if ((a > b) == up) {
+          keys[lo] = b;
+          keys[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int rs = table_stride(w);
+  int32_t* __restrict__ row = table_pool + J.out_off + (int64_t)i * rs;
+  for (int x = tid; x < rs; x += kBlock) row[x] = x < w ? (int32_t)(keys[x] & 0xffffffffu) : -1;
+}
+
 // Work items are taken in list order (the host lists them longest first).
 // With next == nullptr each workgroup takes items blockIdx.x, +gridDim.x, ...;
 // otherwise workgroups pull the next item from an atomic counter that starts
@@ -877,16 +1095,17 @@ __global__ __launch_bounds__(kBlock) void k_crossmap(
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
     const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
     const double* __restrict__ tgt_pool, Moments* __restrict__ partial,
-    int query_set, int window, Dump dump) {
+    int query_set, int window, Dump dump, TableArgs ta) {
   __shared__ Moments red[kBlock];
   __shared__ int s_next;
+  extern __shared__ uint32_t table_lds[];   // bitmask words, then accepted indices
   int it = xcd_item(blockIdx.x, gridDim.x);
   while (it < n_items) {
     const Item I = items[it];
     const Realization R = rzs[I.rz];
     crossmap_item<E, Q, MODE, DUMP>(R, I.tile, emb_pool, pts_pool, pj_pool,
                                     qord_pool, start_pool, tgt_pool, partial,
-                                    query_set, window, dump, red);
+                                    query_set, window, dump, red, ta, table_lds);
     if (next == nullptr) {
       it += gridDim.x;
     } else {
@@ -907,16 +1126,17 @@ __global__ __launch_bounds__(kBlock) void k_crossmap_multi(
     const float* __restrict__ emb_pool, const float* __restrict__ pts_pool,
     const int32_t* __restrict__ pj_pool, const int32_t* __restrict__ qord_pool,
     const int32_t* __restrict__ start_pool, const double* __restrict__ tt,
-    int m_series, Sums* __restrict__ partial, int query_set, int window) {
+    int m_series, Sums* __restrict__ partial, int query_set, int window, TableArgs ta) {
   __shared__ __align__(16) unsigned char lds[MultiLds<E>::kBytes];
   __shared__ int s_next;
+  extern __shared__ uint32_t table_lds[];   // bitmask words, then accepted indices
   int it = xcd_item(blockIdx.x, gridDim.x);
   while (it < n_items) {
     const Item I = items[it];
     const Realization R = rzs[I.rz];
     crossmap_multi_item<E, Q, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool,
                                     start_pool, tt, m_series, self_of[I.rz], partial,
-                                    query_set, window, lds);
+                                    query_set, window, lds, ta, table_lds);
     if (next == nullptr) {
       it += gridDim.x;
     } else {
@@ -983,7 +1203,7 @@ __global__ void k_finalize(const Realization* __restrict__ rzs, int64_t n_rz,
 using CrossmapFn = void (*)(const Realization*, const Item*, int, int*,
                             const float*, const float*, const int32_t*,
                             const int32_t*, const int32_t*, const double*,
-                            Moments*, int, int, Dump);
+                            Moments*, int, int, Dump, TableArgs);
 
 template <int E, int Q>
 struct QSet {
@@ -1031,6 +1251,13 @@ static CrossmapFn crossmap_kernel(int E, int mode, bool dump, int* q_out) {
 // ---------------------------------------------------------------------------
 // host-side launchers (the runtime calls only these)
 // ---------------------------------------------------------------------------
+
+// Dynamic LDS of a cross-map launch whose realizations walk tables over at
+// most n_e points: the library bitmask, then E+1 accepted indices per lane.
+static inline int table_lds_words(int n_e) { return n_e > 0 ? (n_e + 31) / 32 : 0; }
+static inline size_t table_lds_bytes(int E, int n_e) {
+  return n_e > 0 ? (size_t)table_lds_words(n_e) * 4 + (size_t)(E + 1) * kBlock * 4 : 0;
+}
 
 static inline unsigned blocks_for(int64_t n, int per) {
   int64_t b = (n + per - 1) / per;
@@ -1113,19 +1340,39 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_table_build(int E, const TableJob* jobs, int n_jobs, int max_n_e,
+                              const float* emb, int32_t* table, hipStream_t st) {
+  if (n_jobs <= 0 || max_n_e <= 0) return hipSuccess;
+  const dim3 grid((unsigned)max_n_e, (unsigned)n_jobs);
+  switch (E) {
+#define CCM_TCASE(e)                                                        \
+  case e:                                                                   \
+    k_table_build<e><<<grid, kBlock, 0, st>>>(jobs, emb, table);            \
+    break;
+    CCM_TCASE(1) CCM_TCASE(2) CCM_TCASE(3) CCM_TCASE(4) CCM_TCASE(5)
+    CCM_TCASE(6) CCM_TCASE(7) CCM_TCASE(8) CCM_TCASE(9) CCM_TCASE(10)
+#undef CCM_TCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
                            const Realization* rzs, const Item* items,
                            int n_items, int* next, const float* emb,
                            const float* pts, const int32_t* pj,
                            const int32_t* qord, const int32_t* start,
                            const double* tgt, Moments* partial, int query_set,
-                           int window, Dump d, hipStream_t st) {
+                           int window, Dump d, const int32_t* table, int table_n_e,
+                           hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   CrossmapFn f = crossmap_kernel(E, mode, dump, nullptr);
   if (!f) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), 0, st, rzs, items,
-                     n_items, next, emb, pts, pj, qord, start, tgt, partial,
-                     query_set, window, d);
+  const TableArgs ta{table, table_lds_words(table_n_e), 0};
+  hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), table_lds_bytes(E, table_n_e), st,
+                     rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial,
+                     query_set, window, d, ta);
   return hipGetLastError();
 }
 
@@ -1135,23 +1382,26 @@ static hipError_t launch_multi_e(int mode, int grid, const Realization* rzs,
                                  int* next, const float* emb, const float* pts,
                                  const int32_t* pj, const int32_t* qord, const int32_t* start,
                                  const double* tt, int m_series,
-                                 Sums* partial, int query_set, int window, hipStream_t st) {
+                                 Sums* partial, int query_set, int window,
+                                 const int32_t* table, int table_n_e, hipStream_t st) {
   constexpr int Q = DefaultQ<E>::Q;
+  const TableArgs ta{table, table_lds_words(table_n_e), 0};
+  const size_t dyn = table_lds_bytes(E, table_n_e);
   switch (mode) {
     case kExclSelf:
-      k_crossmap_multi<E, Q, kExclSelf><<<grid, kBlock, 0, st>>>(
+      k_crossmap_multi<E, Q, kExclSelf><<<grid, kBlock, dyn, st>>>(
           rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
-          partial, query_set, window);
+          partial, query_set, window, ta);
       break;
     case kKeepSelf:
-      k_crossmap_multi<E, Q, kKeepSelf><<<grid, kBlock, 0, st>>>(
+      k_crossmap_multi<E, Q, kKeepSelf><<<grid, kBlock, dyn, st>>>(
           rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
-          partial, query_set, window);
+          partial, query_set, window, ta);
       break;
     default:
-      k_crossmap_multi<E, Q, kWindow><<<grid, kBlock, 0, st>>>(
+      k_crossmap_multi<E, Q, kWindow><<<grid, kBlock, dyn, st>>>(
           rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
-          partial, query_set, window);
+          partial, query_set, window, ta);
       break;
   }
   return hipGetLastError();
@@ -1179,14 +1429,16 @@ hipError_t launch_crossmap_multi(int E, int mode, int grid, const Realization* r
                                  int* next, const float* emb, const float* pts,
                                  const int32_t* pj, const int32_t* qord, const int32_t* start,
                                  const double* tt, int m_series,
-                                 void* partial, int query_set, int window, hipStream_t st) {
+                                 void* partial, int query_set, int window,
+                                 const int32_t* table, int table_n_e, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   Sums* ps = static_cast<Sums*>(partial);
   switch (E) {
 #define CCM_MCASE(e)                                                                     \
   case e:                                                                                \
     return launch_multi_e<e>(mode, grid, rzs, self_of, items, n_items, next, emb, pts, pj, \
-                             qord, start, tt, m_series, ps, query_set, window, st);
+                             qord, start, tt, m_series, ps, query_set, window, table,   \
+                             table_n_e, st);
     CCM_MCASE(1) CCM_MCASE(2) CCM_MCASE(3) CCM_MCASE(4) CCM_MCASE(5)
     CCM_MCASE(6) CCM_MCASE(7) CCM_MCASE(8) CCM_MCASE(9) CCM_MCASE(10)
 #undef CCM_MCASE

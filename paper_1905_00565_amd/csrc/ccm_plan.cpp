@@ -18,6 +18,63 @@ int64_t order_set(Plan& p, int series, int32_t tau) {
   return off;
 }
 
+// A realization walks a table when the flag asks for it, its embedding fits
+// the walk's LDS bitmask, the expected walk to E+1 acceptable library members
+// ((E+1+excluded) n_e / l_eff row entries) is at most a quarter of a
+// truncated row (a wavefront whose walk runs short scans instead, which must
+// stay rare), and the walk (about 8 instructions per entry) is cheaper than
+// the scan (2E per pair).
+bool use_table(const Plan& p, int E, int64_t ne, int64_t le) {
+  if (!(p.spec.flags & CCM_FLAG_TABLE) || ne > kTableMaxNe) return false;
+  const double excl =
+      p.mode == kExclSelf ? 1.0 : (p.mode == kWindow ? 2.0 * p.window + 1.0 : 0.0);
+  const double walk = (E + 1 + excl) * (double)ne / (double)le;
+  const int64_t w = std::min<int64_t>(kTableWidth, ne);
+  if (w < ne && walk > (double)w / 4.0) return false;
+  return 8.0 * walk < 2.0 * E * (double)le;
+}
+
+int64_t table_for(Plan& p, int64_t emb_off, int64_t ne, int E) {
+  for (const TableJob& t : p.tables)
+    if (t.emb_off == emb_off) return t.out_off;
+  const int32_t w = (int32_t)std::min<int64_t>(kTableWidth, ne);
+  TableJob t{};
+  t.emb_off = emb_off;
+  t.out_off = p.n_table;
+  t.n_e = (int32_t)ne;
+  t.E = E;
+  t.w = w;
+  if (p.te_count[E] == 0) p.te_first[E] = (int)p.tables.size();
+  p.te_count[E] += 1;
+  p.te_max_ne[E] = std::max(p.te_max_ne[E], (int)ne);
+  p.tables.push_back(t);
+  p.n_table += ne * table_row_stride(w);
+  return t.out_off;
+}
+
+// Items grouped by E, the costliest first within a group: a scan costs
+// n_query * l_eff pairs, a table walk about n_query * (E+1) n_e / l_eff
+// row entries.
+static void order_items(Plan& p) {
+  auto cost = [&](const Realization& R) {
+    return R.table_off >= 0 ? (double)R.n_query * (R.E + 1) * R.n_e / R.l_eff / 8.0
+                            : (double)R.n_query * R.l_eff;
+  };
+  std::vector<int32_t> order(p.rz.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (p.rz[a].E != p.rz[b].E) return p.rz[a].E < p.rz[b].E;
+    return cost(p.rz[a]) > cost(p.rz[b]);
+  });
+  for (int32_t idx : order) {
+    const Realization& R = p.rz[idx];
+    if (p.e_count[R.E] == 0) p.e_first[R.E] = (int)p.items.size();
+    for (int t = 0; t < R.n_tiles; ++t) p.items.push_back({idx, t});
+    p.e_count[R.E] += R.n_tiles;
+  }
+  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
+}
+
 // Validate a sweep and lay out every realization of it.
 Plan make_plan(const Spec& s) {
   if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
@@ -97,6 +154,13 @@ Plan make_plan(const Spec& s) {
             R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
             R.slot_base = p.n_slots;
             R.out_index = ((((int64_t)dir * nE + ie) * nT + it) * nL + il) * s.r + ri;
+            R.table_off = -1;
+            if (use_table(p, E, ne, le)) {
+              R.table_off = table_for(p, R.emb_off, ne, E);
+              R.table_w = (int32_t)std::min<int64_t>(kTableWidth, ne);
+              p.e_table_ne[E] = std::max(p.e_table_ne[E], (int)ne);
+              p.table_rz += 1;
+            }
             GatherJob gj{};
             gj.emb_off = R.emb_off;
             gj.lib_off = lib_off;
@@ -132,26 +196,13 @@ Plan make_plan(const Spec& s) {
   }
   if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
 
-  // Items grouped by E; within a group the longest libraries go first.
-  std::vector<int32_t> order(p.rz.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    if (p.rz[a].E != p.rz[b].E) return p.rz[a].E < p.rz[b].E;
-    return p.rz[a].l_eff > p.rz[b].l_eff;
-  });
-  for (int32_t idx : order) {
-    const Realization& R = p.rz[idx];
-    if (p.e_count[R.E] == 0) p.e_first[R.E] = (int)p.items.size();
-    for (int t = 0; t < R.n_tiles; ++t) p.items.push_back({idx, t});
-    p.e_count[R.E] += R.n_tiles;
-  }
-  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
+  order_items(p);
 
   HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
                      p.n_sets, nullptr, nullptr));
   p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
                    p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
-                   (size_t)p.n_ord * 16 +
+                   (size_t)p.n_ord * 16 + p.n_table * 4 + p.tables.size() * sizeof(TableJob) +
                    p.n_slots * sizeof(Moments) + p.n_out * 8 +
                    p.rz.size() * sizeof(Realization) + p.items.size() * sizeof(Item) +
                    p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
@@ -230,6 +281,13 @@ Plan make_plan_matrix(const Spec& s) {
         R.n_tiles = (int32_t)((R.n_query + qt - 1) / qt);
         R.slot_base = p.n_slots;
         R.out_index = (((int64_t)a * M) * nL + il) * s.r + ri;   // target 0 of row a
+        R.table_off = -1;
+        if (use_table(p, E, ne, le)) {
+          R.table_off = table_for(p, R.emb_off, ne, E);
+          R.table_w = (int32_t)std::min<int64_t>(kTableWidth, ne);
+          p.e_table_ne[E] = std::max(p.e_table_ne[E], (int)ne);
+          p.table_rz += 1;
+        }
         GatherJob gj{};
         gj.emb_off = R.emb_off;
         gj.lib_off = lib_off[(size_t)il * s.r + ri];
@@ -259,22 +317,15 @@ Plan make_plan_matrix(const Spec& s) {
         p.flops += pairs * (3.0 * E - 1.0);
         p.preds += nq * (M - 1);
       }
-  std::vector<int32_t> order(p.rz.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return p.rz[x].l_eff > p.rz[y].l_eff; });
-  p.e_first[E] = 0;
-  for (int32_t idx : order)
-    for (int t = 0; t < p.rz[idx].n_tiles; ++t) p.items.push_back({idx, t});
-  p.e_count[E] = (int)p.items.size();
-  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
+  order_items(p);
   HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
                      p.n_sets, nullptr, nullptr));
   p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_ord * 16 + p.n_emb * 4 + p.n_lib * 4 +
                    p.n_pts * 4 +
                    p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
                    p.n_slots * M * multi_sums_bytes() + p.n_out * 8 +
-                   N * target_stride(M) * 8 +
+                   N * target_stride(M) * 8 + p.n_table * 4 +
+                   p.tables.size() * sizeof(TableJob) +
                    p.rz.size() * (sizeof(Realization) + 4) + p.items.size() * sizeof(Item) +
                    p.sample.size() * sizeof(SampleJob) + p.gather.size() * sizeof(GatherJob);
   return p;

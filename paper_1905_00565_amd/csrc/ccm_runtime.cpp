@@ -73,6 +73,10 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
   }
   upload(ex->d_segoff, p.seg_off);
   upload(ex->d_orders, p.orders);
+  if (!p.tables.empty()) {
+    upload(ex->d_tables, p.tables);
+    ex->d_table.ensure(p.n_table * 4);
+  }
   ex->d_s64.ensure(p.n64 * 8);
   ex->d_s32.ensure(p.n32 * 4);
   ex->d_iota.ensure(p.n_ord * 4);
@@ -130,6 +134,11 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
   const bool plain = (p.spec.flags & CCM_FLAG_PLAIN) != 0;
   const bool persistent = (p.spec.flags & CCM_FLAG_PERSISTENT) != 0;
   const Dump nodump{nullptr, nullptr, nullptr};
+  const int32_t* table = ex->d_table.as<int32_t>();
+  for (int E = 1; E <= kMaxE; ++E)
+    HIPCHK(launch_table_build(E, ex->d_tables.as<TableJob>() + p.te_first[E], p.te_count[E],
+                              p.te_max_ne[E], ex->d_emb.as<float>(), ex->d_table.as<int32_t>(),
+                              st));
   if (!plain) {
     HIPCHK(launch_sample(ex->d_sample.as<SampleJob>(), (int64_t)p.sample.size(),
                          ex->d_lib.as<int32_t>(), st));
@@ -160,7 +169,7 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                      ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
                                      ex->d_start.as<int32_t>(), ex->d_tt.as<double>(),
                                      p.spec.M, ex->d_partial.p, p.spec.query_set,
-                                     p.window, st));
+                                     p.window, table, p.e_table_ne[E], st));
       else
         HIPCHK(launch_crossmap(E, p.mode, false, grid, ex->d_rz.as<Realization>(),
                                ex->d_items.as<Item>() + p.e_first[E], n, next,
@@ -168,7 +177,7 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
                                ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
                                ex->d_partial.as<Moments>(), p.spec.query_set, p.window,
-                               nodump, st));
+                               nodump, table, p.e_table_ne[E], st));
       if (timed) {
         HIPCHK(hipEventRecord(ev.b, st));
         c->ev_pending.push_back(ev);
@@ -203,7 +212,8 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                      ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
                                      ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
                                      ex->d_tt.as<double>(), p.spec.M,
-                                     ex->d_partial.p, p.spec.query_set, p.window, st));
+                                     ex->d_partial.p, p.spec.query_set, p.window, table,
+                                     R.table_off >= 0 ? R.n_e : 0, st));
       else
         HIPCHK(launch_crossmap(R.E, p.mode, false, R.n_tiles, ex->d_rz.as<Realization>(),
                                ex->d_plain_items.as<Item>() + ex->plain_first[r],
@@ -211,7 +221,8 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
                                ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
                                ex->d_s64.as<double>(), ex->d_partial.as<Moments>(),
-                               p.spec.query_set, p.window, nodump, st));
+                               p.spec.query_set, p.window, nodump, table,
+                               R.table_off >= 0 ? R.n_e : 0, st));
       if (timed) {
         HIPCHK(hipEventRecord(ev.b, st));
         c->ev_pending.push_back(ev);
@@ -261,6 +272,7 @@ void run(ccm_ctx* c, Exec* ex, hipStream_t st) {
     c->prof.flops += p.flops;
     c->prof.predictions += p.preds;
     c->prof.realizations += (double)p.rz.size();
+    c->prof.table_realizations += (double)p.table_rz;
   }
 }
 
@@ -493,7 +505,13 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     g.query_set = qs;
     g.sorted = sorted;
     std::vector<GatherJob> gj{g};
+    // CCM_FLAG_TABLE: the realization walks a table over the embedding
+    // whatever its size (the hook exercises the walk and its fallback).
+    const bool tab = opts && (opts->flags & CCM_FLAG_TABLE) && ne <= kTableMaxNe;
+    const int32_t tw = (int32_t)std::min<int64_t>(kTableWidth, ne);
     Realization R{};
+    R.table_off = tab ? 0 : -1;
+    R.table_w = tw;
     R.tgt_off = N;
     R.E = E;
     R.tau = tau;
@@ -511,6 +529,16 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     upload(d_gather, gj);
     upload(d_rz, rv);
     upload(d_items, items);
+    DevBuf d_tj, d_tab;
+    if (tab) {
+      TableJob tj{};
+      tj.n_e = (int32_t)ne;
+      tj.E = E;
+      tj.w = tw;
+      std::vector<TableJob> tv{tj};
+      upload(d_tj, tv);
+      d_tab.ensure(ne * table_row_stride(tw) * 4);
+    }
     d_s64.ensure(2 * N * 8);
     d_s32.ensure(N * 4);
     d_iota.ensure(N * 4);
@@ -549,12 +577,16 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     HIPCHK(launch_gather(d_gather.as<GatherJob>(), 1, sorted ? ne : 0, d_emb.as<float>(),
                          d_lib.as<int32_t>(), d_order.as<int32_t>(), d_pts.as<float>(),
                          d_pj.as<int32_t>(), d_start.as<int32_t>(), st));
+    if (tab)
+      HIPCHK(launch_table_build(E, d_tj.as<TableJob>(), 1, (int)ne, d_emb.as<float>(),
+                                d_tab.as<int32_t>(), st));
     Dump dump{d_nbr.as<int32_t>(), d_d2.as<float>(), d_pred.as<double>()};
     HIPCHK(launch_crossmap(E, excl_mode(excl), true, n_tiles, d_rz.as<Realization>(),
                            d_items.as<Item>(), n_tiles, nullptr, d_emb.as<float>(),
                            d_pts.as<float>(), d_pj.as<int32_t>(), d_qord.as<int32_t>(),
                            d_start.as<int32_t>(), d_s64.as<double>(),
-                           d_partial.as<Moments>(), qs, excl > 0 ? excl : 0, dump, st));
+                           d_partial.as<Moments>(), qs, excl > 0 ? excl : 0, dump,
+                           d_tab.as<int32_t>(), tab ? (int)ne : 0, st));
     HIPCHK(launch_finalize(d_rz.as<Realization>(), 1, d_partial.as<Moments>(),
                            d_out.as<double>(), st));
     std::vector<int32_t> hn(ne * K);

@@ -432,7 +432,7 @@ void scheduler_loop(ccm_server* s) {
                                s->items_dev[buf].as<Item>() + pos, n, nullptr, fa, fa, ia, ia,
                                s->slots_start.as<int32_t>(), da,
                                s->slots_partial.as<Moments>(), kv.first.qs, kv.first.window,
-                               nodump, es));
+                               nodump, nullptr, 0, es));
         pos += n;
       }
       HIPCHK(hipEventRecord(s->epoch_ev[buf], es));

@@ -10,10 +10,10 @@
 #pragma once
 
 #ifndef CCM_TUNE_Q
-#define CCM_TUNE_Q {0, 4, 4, 4, 4, 3, 4, 4, 3, 3, 2}
+#define CCM_TUNE_Q {0, 3, 4, 4, 4, 3, 4, 4, 3, 3, 2}
 #endif
 #ifndef CCM_TUNE_G
-#define CCM_TUNE_G {0, 16, 8, 8, 8, 4, 4, 3, 3, 4, 3}
+#define CCM_TUNE_G {0, 16, 8, 8, 6, 6, 6, 4, 4, 4, 3}
 #endif
 
 namespace ccmk {

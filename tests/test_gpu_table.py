@@ -1,0 +1,132 @@
+"""Distance indexing table (CCM_FLAG_TABLE, Section 3.2) against the scan.
+
+Walking a query's table row to its first E+1 library members selects exactly
+the neighbours the brute-force scan selects, so neighbours, squared
+distances, predictions and rho must agree bit for bit with the flag off (the
+brute-force side is pinned to the oracle in test_gpu_parity).  The cases
+cover rows shorter than the series (walks that run short and fall back to
+the scan), full rows, ties and zero distances, every exclusion mode, library
+queries, every form of the batched call and the causal matrix.
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+from paper_1905_00565_amd import capi, synth
+
+pytestmark = pytest.mark.gpu
+TABLE = capi.CCM_FLAG_TABLE
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = capi.Context(0)
+    yield c
+    c.close()
+
+
+def bitwise_equal(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape and a.dtype == b.dtype
+    return np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def series(kind, n, rng):
+    if kind == "logistic":
+        x, y = synth.coupled_logistic(n, *rng.uniform(0.1, 0.9, 2))
+        return x, y
+    if kind == "quantised":
+        return synth.quantised_series(n, 6, rng), synth.quantised_series(n, 9, rng)
+    if kind == "dyadic":
+        return synth.dyadic_series(n, rng), rng.standard_normal(n)
+    return rng.standard_normal(n), rng.standard_normal(n)
+
+
+# (N, E, tau, L, exclusion_radius, query_set, kind)
+NEIGHBOR_CASES = [
+    (3000, 3, 1, 2500, 0, 0, "logistic"),     # long rows truncated to 1024, walk succeeds
+    (3000, 3, 1, 6, 0, 0, "logistic"),        # walk runs short: every wavefront scans
+    (3000, 4, 2, 60, 0, 0, "logistic"),       # some wavefronts short, some not
+    (800, 2, 1, 50, 0, 0, "logistic"),        # rows hold the whole embedding
+    (2500, 10, 2, 2000, 0, 0, "logistic"),
+    (2000, 3, 1, 1500, 0, 0, "quantised"),    # ties and d_1 = 0
+    (1500, 2, 1, 700, 0, 0, "dyadic"),
+    (2000, 3, 1, 1200, -1, 0, "logistic"),    # query kept
+    (2000, 3, 1, 1200, 4, 0, "logistic"),     # exclusion window
+    (2000, 5, 1, 1500, 0, 1, "gauss"),        # library points as queries
+    (1200, 1, 1, 900, 0, 0, "quantised"),
+]
+
+
+@pytest.mark.parametrize("case", NEIGHBOR_CASES, ids=[str(c) for c in NEIGHBOR_CASES])
+def test_table_neighbors_bitwise(ctx, case):
+    N, E, tau, L, excl, qs, kind = case
+    rng = np.random.default_rng(zlib.crc32(repr(case).encode()))
+    S, T = series(kind, N, rng)
+    ne = N - (E - 1) * tau
+    lib = np.sort(rng.choice(ne, size=min(L, ne), replace=False)).astype(np.int32)
+    a = ctx.ccm_neighbors(S, T, E, tau, lib, exclusion_radius=excl, query_set=qs)
+    b = ctx.ccm_neighbors(S, T, E, tau, lib, exclusion_radius=excl, query_set=qs, flags=TABLE)
+    assert np.array_equal(a[0], b[0])
+    assert bitwise_equal(a[1], b[1])
+    assert bitwise_equal(a[2], b[2])
+    assert a[3] == b[3] or (np.isnan(a[3]) and np.isnan(b[3]))
+
+
+def sweep(ctx, X, Y, E, tau, L, r, seed, **k):
+    ctx.profile_enable(True)
+    ctx.profile_read(reset=True)
+    out = ctx.ccm_sweep(X, Y, E, tau, L, r, seed, **k)
+    p = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    return out, p
+
+
+@pytest.mark.parametrize("flags,excl,qs", [
+    (0, 0, 0), (capi.CCM_FLAG_PERSISTENT, 0, 0), (capi.CCM_FLAG_NO_GRAPH, 0, 0),
+    (0, 2, 0), (0, -1, 0), (0, 0, 1)])
+def test_table_sweep_bitwise(ctx, flags, excl, qs):
+    X, Y = synth.coupled_logistic(4000)
+    E, tau = [1, 2, 3, 5, 8], [1, 3]
+    L = synth.geometric_grid(50, 4000, 8)
+    a, pa = sweep(ctx, X, Y, E, tau, L, 6, 11, exclusion_radius=excl, query_set=qs,
+                  flags=flags)
+    b, pb = sweep(ctx, X, Y, E, tau, L, 6, 11, exclusion_radius=excl, query_set=qs,
+                  flags=flags | TABLE)
+    assert pa["table_realizations"] == 0
+    assert pb["table_realizations"] > 0.3 * pb["realizations"]
+    assert bitwise_equal(a, b)
+
+
+def test_table_plain_form(ctx):
+    X, Y = synth.coupled_logistic(2500)
+    L = [60, 800, 2500]
+    a = ctx.ccm(X, Y, 4, 2, L, 3, 5)
+    b = ctx.ccm(X, Y, 4, 2, L, 3, 5, flags=capi.CCM_FLAG_PLAIN | TABLE)
+    c = ctx.ccm(X, Y, 4, 2, L, 3, 5, flags=TABLE)
+    for u, v, w in zip(a[:2], b[:2], c[:2]):
+        assert bitwise_equal(u, v) and bitwise_equal(u, w)
+
+
+def test_table_matrix(ctx):
+    S, _ = synth.logistic_network(6, 3000, seed=5)
+    L = [150, 1200, 3000]
+    ctx.profile_enable(True)
+    ctx.profile_read(reset=True)
+    a = ctx.ccm_matrix(S, 3, 1, L, 3, 9)
+    b = ctx.ccm_matrix(S, 3, 1, L, 3, 9, flags=TABLE)
+    p = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    assert p["table_realizations"] > 0
+    assert bitwise_equal(a, b)
+
+
+def test_table_long_series_sample(ctx):
+    """Rows truncated far below the series length (N = 10^5)."""
+    w = synth.workload_long(r=2)
+    L = [1000, 50000, 100000]
+    a = ctx.ccm(w.X, w.Y, 3, 2, L, 2, w.seed)
+    b = ctx.ccm(w.X, w.Y, 3, 2, L, 2, w.seed, flags=TABLE)
+    for u, v in zip(a[:2], b[:2]):
+        assert bitwise_equal(u, v)

@@ -15,7 +15,8 @@ flops per pair 3E-1, over the summed HIP-event duration of its launches; HBM
 traffic from the committed counter summary when it matches the kernel
 sources), the other workloads of the method (`workloads`: small coupled map
 with plain vs batched launches, long noisy series, 64-series causal matrix),
-the run-time elasticity study (`elasticity`), the served form's p50/p99 job
+the run-time elasticity study (`elasticity`), the same workloads through the
+paper's distance indexing table (`index_table`), the served form's p50/p99 job
 latency on a Poisson job stream (`served`), and the CPU oracle timed on a
 bounded random sample of the same realizations.
 """
@@ -206,6 +207,49 @@ def workloads_leg(ctx, torch, dev, stream):
                          (matrix(1, rho1), matrix(1, rho1, capi.CCM_FLAG_PLAIN)), 1,
                          "r = 1 (640 neighbour searches, 40 320 rho values)")
     return res
+
+
+def table_leg(ctx, torch, dev, stream, steps=3):
+    """The distance indexing table (Section 3.2, flag CCM_FLAG_TABLE) on the
+    sweep, the long series and the causal matrix: same results bit for bit
+    as the brute-force path (tested); realizations with a short expected
+    walk use it, the rest scan.  Wall time per call includes building the
+    tables."""
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = {}
+    w = synth.workload_sweep()
+    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+    rho = torch.empty((2, len(w.E), len(w.tau), len(w.L), w.r), **f64)
+    fn = lambda: ctx.ccm_sweep_dev(X, Y, w.E, w.tau, w.L, w.r, w.seed, rho, stream=stream,
+                                   flags=capi.CCM_FLAG_TABLE)
+    el, _ = _timed(ctx, torch, fn, steps, False)
+    _, p = _timed(ctx, torch, fn, 1, True)
+    out["sweep"] = {"workload": w.name, "ms_per_call": el * 1e3,
+                    "predictions_per_sec": p["predictions"] / el,
+                    "rho_realizations_per_sec": p["realizations"] / el,
+                    "table_realization_share": p["table_realizations"] / p["realizations"]}
+    w = synth.workload_long()
+    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+    a, b = torch.empty((len(w.L), w.r), **f64), torch.empty((len(w.L), w.r), **f64)
+    fn = lambda: ctx.ccm_dev(X, Y, w.E[0], w.tau[0], w.L, w.r, w.seed, a, b, stream=stream,
+                             flags=capi.CCM_FLAG_TABLE)
+    el, _ = _timed(ctx, torch, fn, 1, False)
+    _, p = _timed(ctx, torch, fn, 1, True)
+    out["long"] = {"workload": w.name, "ms_per_call": el * 1e3,
+                   "predictions_per_sec": p["predictions"] / el,
+                   "table_realization_share": p["table_realizations"] / p["realizations"]}
+    m = synth.workload_matrix()
+    S = torch.tensor(m["S"], device=dev)
+    M = S.shape[0]
+    rho = torch.empty((M, M, len(m["L"]), m["r"]), **f64)
+    fn = lambda: ctx.ccm_matrix_dev(S, m["E"], m["tau"], m["L"], m["r"], m["seed"], rho,
+                                    stream=stream, flags=capi.CCM_FLAG_TABLE)
+    el, _ = _timed(ctx, torch, fn, 1, False)
+    _, p = _timed(ctx, torch, fn, 1, True)
+    out["matrix"] = {"workload": m["name"], "ms_per_call": el * 1e3,
+                     "predictions_per_sec": p["predictions"] / el,
+                     "table_realization_share": p["table_realizations"] / p["realizations"]}
+    return out
 
 
 def elasticity_leg(ctx, torch, dev, stream, reps=3):
@@ -401,6 +445,7 @@ def main():
         print("bench: other workloads and the elasticity study", file=sys.stderr, flush=True)
         out["workloads"] = workloads_leg(ctx, torch, dev, stream)
         out["elasticity"] = elasticity_leg(ctx, torch, dev, stream)
+        out["index_table"] = table_leg(ctx, torch, dev, stream)
     if a.serve_jobs > 0:
         print(f"bench: served leg, {a.serve_jobs} jobs", file=sys.stderr, flush=True)
         ctx.profile_enable(False)

@@ -34,7 +34,7 @@ TUNE_DIR = os.path.join(B.PKG, "_tune")
 # (Q, G) candidates per E; the first is the current table's choice.
 CANDIDATES = {
     1: [(3, 16), (4, 16), (4, 8), (4, 12), (2, 16), (4, 24)],
-    2: [(4, 8), (4, 16), (4, 12), (4, 6), (3, 8), (2, 16)],
+    2: [(4, 12), (4, 8), (4, 16), (4, 6), (3, 8), (2, 16)],
     3: [(4, 8), (4, 12), (4, 6), (3, 8), (4, 4), (2, 16)],
     4: [(4, 6), (4, 8), (4, 12), (3, 8), (4, 4), (2, 12)],
     5: [(3, 6), (3, 4), (4, 4), (2, 8), (3, 8), (4, 6)],

@@ -593,7 +593,7 @@ __device__ __forceinline__ void table_bitmask(const Realization& R,
   __syncthreads();
 }
 
-template <int E, int Q, int MODE>
+template <int E, int Q, int MODE, bool TBL>
 __device__ __forceinline__ void scan_library(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
@@ -637,14 +637,17 @@ __device__ __forceinline__ void scan_library(
   if (!__builtin_amdgcn_ballot_w64(any)) return;
 
   // Table walk (the realization's rows exist): done unless a row ran short.
-  if (R.table_off >= 0 && ta.words > 0) {
-    if (walk_table<E, Q, MODE>(R, ta.pool, tlds, reinterpret_cast<int32_t*>(tlds + ta.words),
-                               emb, window, S))
-      return;
+  // Compiled only into the launches that carry tables.
+  if constexpr (TBL) {
+    if (R.table_off >= 0 && ta.words > 0) {
+      if (walk_table<E, Q, MODE>(R, ta.pool, tlds, reinterpret_cast<int32_t*>(tlds + ta.words),
+                                 emb, window, S))
+        return;
 #pragma unroll
-    for (int m = 0; m < Q; ++m)
+      for (int m = 0; m < Q; ++m)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
+        for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
+    }
   }
 
   // Brute-force scan of every library position, outward from the
@@ -718,7 +721,7 @@ __device__ __forceinline__ void simplex_weights(const float (&nd)[K], double (&w
   for (int t = 0; t < K; ++t) w[t] = u[t] / su;
 }
 
-template <int E, int Q, int MODE, bool DUMP>
+template <int E, int Q, int MODE, bool DUMP, bool TBL>
 __device__ __forceinline__ void crossmap_item(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
@@ -731,10 +734,11 @@ __device__ __forceinline__ void crossmap_item(
   const double* __restrict__ tgt = tgt_pool + R.tgt_off;
   const int64_t off = (int64_t)(E - 1) * R.tau;     // time of embedded point 0
 
-  if (R.table_off >= 0 && ta.words > 0) table_bitmask(R, pj_pool, tlds);
+  if constexpr (TBL)
+    if (R.table_off >= 0 && ta.words > 0) table_bitmask(R, pj_pool, tlds);
   ScanState<E, Q, MODE> S;
-  scan_library<E, Q, MODE>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
-                           query_set, window, ta, tlds, S);
+  scan_library<E, Q, MODE, TBL>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
+                                query_set, window, ta, tlds, S);
 
   // Simplex projection from the E+1 neighbours, then Pearson moments.
   Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -840,7 +844,7 @@ struct MultiLds {
   static constexpr int kBytes = kStage > kRed ? kStage : kRed;
 };
 
-template <int E, int Q, int MODE>
+template <int E, int Q, int MODE, bool TBL>
 __device__ __forceinline__ void crossmap_multi_item(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
@@ -855,10 +859,11 @@ __device__ __forceinline__ void crossmap_multi_item(
   const int mp = target_stride(m_series);
   const int64_t off = (int64_t)(E - 1) * R.tau;
 
-  if (R.table_off >= 0 && ta.words > 0) table_bitmask(R, pj_pool, tlds);
+  if constexpr (TBL)
+    if (R.table_off >= 0 && ta.words > 0) table_bitmask(R, pj_pool, tlds);
   ScanState<E, Q, MODE> S;
-  scan_library<E, Q, MODE>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
-                           query_set, window, ta, tlds, S);
+  scan_library<E, Q, MODE, TBL>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
+                                query_set, window, ta, tlds, S);
 
   double w[Q][K];
   int32_t nj[Q][K];
@@ -1088,7 +1093,7 @@ __device__ __forceinline__ int xcd_item(int b, int grid) {
   return base + (r % kXcds) * kXcdRun + r / kXcds;
 }
 
-template <int E, int Q, int MODE, bool DUMP>
+template <int E, int Q, int MODE, bool DUMP, bool TBL>
 __global__ __launch_bounds__(kBlock) void k_crossmap(
     const Realization* __restrict__ rzs, const Item* __restrict__ items,
     int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
@@ -1103,7 +1108,7 @@ __global__ __launch_bounds__(kBlock) void k_crossmap(
   while (it < n_items) {
     const Item I = items[it];
     const Realization R = rzs[I.rz];
-    crossmap_item<E, Q, MODE, DUMP>(R, I.tile, emb_pool, pts_pool, pj_pool,
+    crossmap_item<E, Q, MODE, DUMP, TBL>(R, I.tile, emb_pool, pts_pool, pj_pool,
                                     qord_pool, start_pool, tgt_pool, partial,
                                     query_set, window, dump, red, ta, table_lds);
     if (next == nullptr) {
@@ -1119,7 +1124,7 @@ __global__ __launch_bounds__(kBlock) void k_crossmap(
 
 // Causal-matrix form: realization rz searches the manifold of series
 // R.emb_off's owner (index self_of[rz]) and predicts all m_series series.
-template <int E, int Q, int MODE>
+template <int E, int Q, int MODE, bool TBL>
 __global__ __launch_bounds__(kBlock) void k_crossmap_multi(
     const Realization* __restrict__ rzs, const int32_t* __restrict__ self_of,
     const Item* __restrict__ items, int n_items, int* __restrict__ next,
@@ -1134,7 +1139,7 @@ __global__ __launch_bounds__(kBlock) void k_crossmap_multi(
   while (it < n_items) {
     const Item I = items[it];
     const Realization R = rzs[I.rz];
-    crossmap_multi_item<E, Q, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool,
+    crossmap_multi_item<E, Q, MODE, TBL>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool,
                                     start_pool, tt, m_series, self_of[I.rz], partial,
                                     query_set, window, lds, ta, table_lds);
     if (next == nullptr) {
@@ -1205,21 +1210,28 @@ using CrossmapFn = void (*)(const Realization*, const Item*, int, int*,
                             const int32_t*, const int32_t*, const double*,
                             Moments*, int, int, Dump, TableArgs);
 
-template <int E, int Q>
-struct QSet {
+template <int E, int Q, bool TBL>
+struct QSetT {
   static CrossmapFn get(int mode, bool dump) {
     if (dump) {
       switch (mode) {
-        case kExclSelf: return k_crossmap<E, 1, kExclSelf, true>;
-        case kKeepSelf: return k_crossmap<E, 1, kKeepSelf, true>;
-        default: return k_crossmap<E, 1, kWindow, true>;
+        case kExclSelf: return k_crossmap<E, 1, kExclSelf, true, TBL>;
+        case kKeepSelf: return k_crossmap<E, 1, kKeepSelf, true, TBL>;
+        default: return k_crossmap<E, 1, kWindow, true, TBL>;
       }
     }
     switch (mode) {
-      case kExclSelf: return k_crossmap<E, Q, kExclSelf, false>;
-      case kKeepSelf: return k_crossmap<E, Q, kKeepSelf, false>;
-      default: return k_crossmap<E, Q, kWindow, false>;
+      case kExclSelf: return k_crossmap<E, Q, kExclSelf, false, TBL>;
+      case kKeepSelf: return k_crossmap<E, Q, kKeepSelf, false, TBL>;
+      default: return k_crossmap<E, Q, kWindow, false, TBL>;
     }
+  }
+};
+
+template <int E, int Q>
+struct QSet {
+  static CrossmapFn get(int mode, bool dump, bool tbl) {
+    return tbl ? QSetT<E, Q, true>::get(mode, dump) : QSetT<E, Q, false>::get(mode, dump);
   }
 };
 
@@ -1230,14 +1242,14 @@ struct DefaultQ {
   static constexpr int Q = kTuneQ[E];
 };
 
-static CrossmapFn crossmap_kernel(int E, int mode, bool dump, int* q_out) {
+static CrossmapFn crossmap_kernel(int E, int mode, bool dump, bool tbl, int* q_out) {
   int q = 1;
   CrossmapFn f = nullptr;
   switch (E) {
 #define CCM_CASE(e)                                           \
   case e:                                                     \
     q = dump ? 1 : DefaultQ<e>::Q;                            \
-    f = QSet<e, DefaultQ<e>::Q>::get(mode, dump);             \
+    f = QSet<e, DefaultQ<e>::Q>::get(mode, dump, tbl);        \
     break;
     CCM_CASE(1) CCM_CASE(2) CCM_CASE(3) CCM_CASE(4) CCM_CASE(5)
     CCM_CASE(6) CCM_CASE(7) CCM_CASE(8) CCM_CASE(9) CCM_CASE(10)
@@ -1268,7 +1280,7 @@ static inline unsigned blocks_for(int64_t n, int per) {
 
 int crossmap_queries_per_lane(int E, bool dump) {
   int q = 0;
-  crossmap_kernel(E, kExclSelf, dump, &q);
+  crossmap_kernel(E, kExclSelf, dump, false, &q);
   return q;
 }
 
@@ -1367,7 +1379,7 @@ hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
                            int window, Dump d, const int32_t* table, int table_n_e,
                            hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  CrossmapFn f = crossmap_kernel(E, mode, dump, nullptr);
+  CrossmapFn f = crossmap_kernel(E, mode, dump, table_n_e > 0, nullptr);
   if (!f) return hipErrorInvalidValue;
   const TableArgs ta{table, table_lds_words(table_n_e), 0};
   hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), table_lds_bytes(E, table_n_e), st,
@@ -1387,23 +1399,25 @@ static hipError_t launch_multi_e(int mode, int grid, const Realization* rzs,
   constexpr int Q = DefaultQ<E>::Q;
   const TableArgs ta{table, table_lds_words(table_n_e), 0};
   const size_t dyn = table_lds_bytes(E, table_n_e);
+  using MultiFn = void (*)(const Realization*, const int32_t*, const Item*, int, int*,
+                           const float*, const float*, const int32_t*, const int32_t*,
+                           const int32_t*, const double*, int, Sums*, int, int, TableArgs);
+  MultiFn f;
+  const bool tbl = table_n_e > 0;
   switch (mode) {
     case kExclSelf:
-      k_crossmap_multi<E, Q, kExclSelf><<<grid, kBlock, dyn, st>>>(
-          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
-          partial, query_set, window, ta);
+      f = tbl ? k_crossmap_multi<E, Q, kExclSelf, true> : k_crossmap_multi<E, Q, kExclSelf, false>;
       break;
     case kKeepSelf:
-      k_crossmap_multi<E, Q, kKeepSelf><<<grid, kBlock, dyn, st>>>(
-          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
-          partial, query_set, window, ta);
+      f = tbl ? k_crossmap_multi<E, Q, kKeepSelf, true> : k_crossmap_multi<E, Q, kKeepSelf, false>;
       break;
     default:
-      k_crossmap_multi<E, Q, kWindow><<<grid, kBlock, dyn, st>>>(
-          rzs, self_of, items, n_items, next, emb, pts, pj, qord, start, tt, m_series,
-          partial, query_set, window, ta);
+      f = tbl ? k_crossmap_multi<E, Q, kWindow, true> : k_crossmap_multi<E, Q, kWindow, false>;
       break;
   }
+  hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), dyn, st, rzs, self_of, items,
+                     n_items, next, emb, pts, pj, qord, start, tt, m_series, partial,
+                     query_set, window, ta);
   return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // ccm_tune.h -- launch shape of the cross-map kernel for each embedding
 // dimension E (index 0 unused).  Written by paper_1905_00565_amd/autotune.py
 // from timings of the E = 1..10, tau = 1..5 sweep on coupled-logistic series
-// (N = 10000, r = 50 per (E, tau, L)); the build may override either table with -DCCM_TUNE_Q={...}
+// (N = 10000, r = 250 per (E, tau, L)); the build may override either table with -DCCM_TUNE_Q={...}
 // or -DCCM_TUNE_G={...} (the tuner does, to time candidates).
 //
 //   kTuneQ[E]  queries per lane (a workgroup of 256 lanes holds 256*Q queries)
@@ -13,7 +13,7 @@
 #define CCM_TUNE_Q {0, 3, 4, 4, 4, 3, 4, 4, 3, 3, 2}
 #endif
 #ifndef CCM_TUNE_G
-#define CCM_TUNE_G {0, 16, 8, 8, 6, 6, 6, 4, 4, 4, 3}
+#define CCM_TUNE_G {0, 16, 12, 8, 6, 6, 6, 4, 4, 4, 3}
 #endif
 
 namespace ccmk {

@@ -1,9 +1,10 @@
 """Pick the cross-map kernel's launch shape for each embedding dimension E.
 
-The hot kernel has two shape parameters per E (see ``csrc/ccm_tune.h``):
-Q, the queries each lane holds, and G, the library candidates evaluated per
-trigger check.  Both are compile-time, so candidates are separate builds of
-the kernel translation unit.  Each build ("column") gives every E one
+The hot kernel has three shape parameters per E (see ``csrc/ccm_tune.h``):
+Q, the queries each lane holds; G, the library candidates evaluated per
+trigger check; and W, a minimum of resident wavefronts per SIMD imposed on
+the register allocator (0: none).  All are compile-time, so candidates are
+separate builds of the kernel translation unit.  Each build ("column") gives every E one
 candidate from that E's list; every column is timed on the same sweep and
 each E keeps its fastest candidate.
 
@@ -31,28 +32,32 @@ from . import build as B
 
 TUNE_DIR = os.path.join(B.PKG, "_tune")
 
-# (Q, G) candidates per E; the first is the current table's choice.
+# (Q, G) or (Q, G, W) candidates per E; the first is the current table's choice.
 CANDIDATES = {
-    1: [(3, 16), (4, 16), (4, 8), (4, 12), (2, 16), (4, 24)],
-    2: [(4, 12), (4, 8), (4, 16), (4, 6), (3, 8), (2, 16)],
-    3: [(4, 8), (4, 12), (4, 6), (3, 8), (4, 4), (2, 16)],
-    4: [(4, 6), (4, 8), (4, 12), (3, 8), (4, 4), (2, 12)],
-    5: [(3, 6), (3, 4), (4, 4), (2, 8), (3, 8), (4, 6)],
-    6: [(4, 6), (4, 4), (3, 6), (2, 8), (3, 4), (4, 3)],
-    7: [(4, 4), (4, 3), (3, 4), (2, 6), (3, 6), (2, 8)],
-    8: [(3, 4), (3, 3), (4, 3), (2, 6), (3, 6), (2, 4)],
-    9: [(3, 4), (3, 3), (2, 6), (3, 6), (2, 4), (4, 3)],
-    10: [(2, 3), (2, 4), (3, 3), (2, 6), (3, 4), (2, 8)],
+    1: [(3, 16, 6), (2, 16, 7), (3, 12, 7), (3, 16, 7), (2, 24, 6)],
+    2: [(4, 12, 6), (4, 12, 7), (3, 12, 7), (4, 8, 7), (3, 16, 6)],
+    3: [(4, 8, 6), (4, 8, 7), (3, 8, 7), (4, 6, 7), (3, 12, 6)],
+    4: [(4, 6, 6), (4, 6, 7), (3, 6, 7), (4, 4, 7), (3, 8, 6)],
+    5: [(3, 6, 6), (3, 6, 7), (2, 6, 7), (3, 4, 7), (2, 8, 6)],
+    6: [(3, 4, 6), (3, 4, 7), (2, 4, 7), (2, 6, 6), (3, 3, 7)],
+    7: [(2, 4, 6), (2, 4, 7), (2, 3, 7), (2, 6, 6), (1, 6, 8)],
+    8: [(2, 3, 6), (2, 3, 7), (2, 4, 6), (1, 4, 8), (2, 2, 7)],
+    9: [(2, 3, 6), (2, 3, 7), (2, 4, 6), (1, 4, 8), (2, 2, 7)],
+    10: [(2, 3, 6), (2, 3, 7), (2, 2, 7), (1, 4, 8), (1, 3, 8)],
 }
 
 
 def columns():
+    """Column k gives every E its k-th candidate (or its last, if it has fewer);
+    a candidate is (Q, G) or (Q, G, W)."""
     n = max(len(v) for v in CANDIDATES.values())
     cols = []
     for k in range(n):
-        q = [0] + [CANDIDATES[e][min(k, len(CANDIDATES[e]) - 1)][0] for e in range(1, 11)]
-        g = [0] + [CANDIDATES[e][min(k, len(CANDIDATES[e]) - 1)][1] for e in range(1, 11)]
-        cols.append((q, g))
+        pick = [CANDIDATES[e][min(k, len(CANDIDATES[e]) - 1)] for e in range(1, 11)]
+        q = [0] + [c[0] for c in pick]
+        g = [0] + [c[1] for c in pick]
+        w = [0] + [c[2] if len(c) > 2 else 0 for c in pick]
+        cols.append((q, g, w))
     return cols
 
 
@@ -60,9 +65,10 @@ def _brace(v):
     return "{" + ", ".join(str(x) for x in v) + "}"
 
 
-def _build_column(k, q, g):
+def _build_column(k, q, g, w):
     obj = os.path.join(TUNE_DIR, f"kernels_{k}.o")
     cmd = [B.hipcc(), *B.common_flags(), f"-DCCM_TUNE_Q={_brace(q)}", f"-DCCM_TUNE_G={_brace(g)}",
+           f"-DCCM_TUNE_W={_brace(w)}",
            "-c", os.path.join(B.CSRC, "ccm_kernels.hip"), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -85,7 +91,7 @@ def build_columns(jobs: int = 8):
     os.makedirs(TUNE_DIR, exist_ok=True)
     cols = columns()
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        libs = list(ex.map(lambda a: _build_column(*a), [(k, q, g) for k, (q, g) in enumerate(cols)]))
+        libs = list(ex.map(lambda a: _build_column(*a), [(k, *c) for k, c in enumerate(cols)]))
     with open(os.path.join(TUNE_DIR, "columns.json"), "w") as f:
         json.dump({"columns": cols, "libs": [os.path.basename(x) for x in libs]}, f)
     return libs
@@ -117,20 +123,26 @@ def time_column(r: int, n: int):
     print(json.dumps(out), flush=True)
 
 
-def write_header(path, q, g, note):
+def write_header(path, q, g, w, note):
     text = f"""// ccm_tune.h -- launch shape of the cross-map kernel for each embedding
 // dimension E (index 0 unused).  Written by paper_1905_00565_amd/autotune.py
 // from timings of the E = 1..10, tau = 1..5 sweep on coupled-logistic series
-// ({note}); the build may override either table with -DCCM_TUNE_Q={{...}}
-// or -DCCM_TUNE_G={{...}} (the tuner does, to time candidates).
+// ({note}); the build may override any table with -DCCM_TUNE_Q={{...}},
+// -DCCM_TUNE_G={{...}} or -DCCM_TUNE_W={{...}} (the tuner does, to time
+// candidates).
 //
 //   kTuneQ[E]  queries per lane (a workgroup of 256 lanes holds 256*Q queries)
 //   kTuneG[E]  library candidates per trigger check (one group of G distances
 //              per query, then one compare against its running E+1-th key)
+//   kTuneW[E]  minimum wavefronts per SIMD the compiler must fit (register
+//              budget 512/W per lane); 0 leaves it free
 #pragma once
 
 #ifndef CCM_TUNE_Q
 #define CCM_TUNE_Q {_brace(q)}
+#endif
+#ifndef CCM_TUNE_W
+#define CCM_TUNE_W {_brace(w)}
 #endif
 #ifndef CCM_TUNE_G
 #define CCM_TUNE_G {_brace(g)}
@@ -139,6 +151,7 @@ def write_header(path, q, g, note):
 namespace ccmk {{
 constexpr int kTuneQ[11] = CCM_TUNE_Q;
 constexpr int kTuneG[11] = CCM_TUNE_G;
+constexpr int kTuneW[11] = CCM_TUNE_W;
 }}  // namespace ccmk
 """
     with open(path, "w") as f:
@@ -151,7 +164,7 @@ def time_columns(out: str, r: int, n: int, timeout: int):
     cols, libs = meta["columns"], meta["libs"]
     results = []
     for k, lib in enumerate(libs):
-        print(f"column {k}: Q={cols[k][0][1:]} G={cols[k][1][1:]}", flush=True)
+        print(f"column {k}: Q={cols[k][0][1:]} G={cols[k][1][1:]} W={cols[k][2][1:]}", flush=True)
         env = dict(os.environ, CCM_LIBRARY=os.path.join(TUNE_DIR, lib))
         res = subprocess.run([sys.executable, "-u", "-m", "paper_1905_00565_amd.autotune",
                               "_child", "--r", str(r), "--n", str(n)],
@@ -166,20 +179,21 @@ def time_columns(out: str, r: int, n: int, timeout: int):
         sums = {results[k][e]["rho_sum"] for k in range(len(results))}
         if len({round(s, 9) for s in sums}) != 1:
             raise RuntimeError(f"rho differs between columns at E={e}: {sums}")
-    q, g, report = [0], [0], {}
+    q, g, wv, report = [0], [0], [0], {}
     for e in range(1, 11):
         ms = [results[k][e]["ms"] for k in range(len(results))]
         best = min(range(len(ms)), key=lambda k: ms[k])
         q.append(cols[best][0][e])
         g.append(cols[best][1][e])
-        report[e] = {"choice": [q[-1], g[-1]], "ms": ms,
-                     "candidates": [[cols[k][0][e], cols[k][1][e]] for k in range(len(cols))],
+        wv.append(cols[best][2][e])
+        report[e] = {"choice": [q[-1], g[-1], wv[-1]], "ms": ms,
+                     "candidates": [[cols[k][i][e] for i in range(3)] for k in range(len(cols))],
                      "tflops": results[best][e]["flops"] / ms[best] / 1e9}
-    write_header(out, q, g, f"N = {n}, r = {r} per (E, tau, L)")
+    write_header(out, q, g, wv, f"N = {n}, r = {r} per (E, tau, L)")
     with open(os.path.splitext(out)[0] + ".json", "w") as f:
         json.dump(report, f, indent=1)
     for e in range(1, 11):
-        print(f"E={e}: Q={q[e]} G={g[e]}  {min(report[e]['ms']):.2f} ms "
+        print(f"E={e}: Q={q[e]} G={g[e]} W={wv[e]}  {min(report[e]['ms']):.2f} ms "
               f"({report[e]['tflops']:.1f} TFLOP/s)  candidates ms={['%.2f' % x for x in report[e]['ms']]}")
 
 
@@ -187,7 +201,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("phase", choices=["build", "time", "_child"])
     ap.add_argument("--out", default=os.path.join(B.CSRC, "ccm_tune.h"))
-    ap.add_argument("--r", type=int, default=50)
+    ap.add_argument("--r", type=int, default=250)
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("--timeout", type=int, default=240)

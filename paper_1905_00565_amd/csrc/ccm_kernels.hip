@@ -1094,7 +1094,8 @@ __device__ __forceinline__ int xcd_item(int b, int grid) {
 }
 
 template <int E, int Q, int MODE, bool DUMP, bool TBL>
-__global__ __launch_bounds__(kBlock) void k_crossmap(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(kTuneW[E] > 0 ? kTuneW[E] : 1, 8))) void k_crossmap(
     const Realization* __restrict__ rzs, const Item* __restrict__ items,
     int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,

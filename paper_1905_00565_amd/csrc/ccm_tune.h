@@ -1,22 +1,29 @@
 // ccm_tune.h -- launch shape of the cross-map kernel for each embedding
 // dimension E (index 0 unused).  Written by paper_1905_00565_amd/autotune.py
 // from timings of the E = 1..10, tau = 1..5 sweep on coupled-logistic series
-// (N = 10000, r = 250 per (E, tau, L)); the build may override either table with -DCCM_TUNE_Q={...}
-// or -DCCM_TUNE_G={...} (the tuner does, to time candidates).
+// (N = 10000, r = 250 per (E, tau, L)); the build may override any table with -DCCM_TUNE_Q={...},
+// -DCCM_TUNE_G={...} or -DCCM_TUNE_W={...} (the tuner does, to time
+// candidates).
 //
 //   kTuneQ[E]  queries per lane (a workgroup of 256 lanes holds 256*Q queries)
 //   kTuneG[E]  library candidates per trigger check (one group of G distances
 //              per query, then one compare against its running E+1-th key)
+//   kTuneW[E]  minimum wavefronts per SIMD the compiler must fit (register
+//              budget 512/W per lane); 0 leaves it free
 #pragma once
 
 #ifndef CCM_TUNE_Q
-#define CCM_TUNE_Q {0, 3, 4, 4, 4, 3, 4, 4, 3, 3, 2}
+#define CCM_TUNE_Q {0, 3, 4, 4, 4, 3, 3, 2, 2, 2, 2}
+#endif
+#ifndef CCM_TUNE_W
+#define CCM_TUNE_W {0, 6, 6, 6, 6, 6, 6, 6, 6, 6, 6}
 #endif
 #ifndef CCM_TUNE_G
-#define CCM_TUNE_G {0, 16, 12, 8, 6, 6, 6, 4, 4, 4, 3}
+#define CCM_TUNE_G {0, 16, 12, 8, 6, 6, 4, 4, 3, 3, 3}
 #endif
 
 namespace ccmk {
 constexpr int kTuneQ[11] = CCM_TUNE_Q;
 constexpr int kTuneG[11] = CCM_TUNE_G;
+constexpr int kTuneW[11] = CCM_TUNE_W;
 }  // namespace ccmk

@@ -34,15 +34,15 @@ TUNE_DIR = os.path.join(B.PKG, "_tune")
 
 # (Q, G) or (Q, G, W) candidates per E; the first is the current table's choice.
 CANDIDATES = {
-    1: [(3, 16, 6), (2, 16, 7), (3, 12, 7), (3, 16, 7), (2, 24, 6)],
+    1: [(3, 16, 7), (3, 16, 6), (2, 16, 7), (3, 12, 7), (2, 24, 6)],
     2: [(4, 12, 6), (4, 12, 7), (3, 12, 7), (4, 8, 7), (3, 16, 6)],
     3: [(4, 8, 6), (4, 8, 7), (3, 8, 7), (4, 6, 7), (3, 12, 6)],
     4: [(4, 6, 6), (4, 6, 7), (3, 6, 7), (4, 4, 7), (3, 8, 6)],
     5: [(3, 6, 6), (3, 6, 7), (2, 6, 7), (3, 4, 7), (2, 8, 6)],
-    6: [(3, 4, 6), (3, 4, 7), (2, 4, 7), (2, 6, 6), (3, 3, 7)],
-    7: [(2, 4, 6), (2, 4, 7), (2, 3, 7), (2, 6, 6), (1, 6, 8)],
-    8: [(2, 3, 6), (2, 3, 7), (2, 4, 6), (1, 4, 8), (2, 2, 7)],
-    9: [(2, 3, 6), (2, 3, 7), (2, 4, 6), (1, 4, 8), (2, 2, 7)],
+    6: [(2, 4, 7), (3, 4, 6), (3, 4, 7), (2, 6, 6), (3, 3, 7)],
+    7: [(2, 3, 7), (2, 4, 6), (2, 4, 7), (2, 6, 6), (1, 6, 8)],
+    8: [(2, 4, 6), (2, 3, 6), (2, 3, 7), (1, 4, 8), (2, 2, 7)],
+    9: [(2, 4, 6), (2, 3, 6), (2, 3, 7), (1, 4, 8), (2, 2, 7)],
     10: [(2, 3, 6), (2, 3, 7), (2, 2, 7), (1, 4, 8), (1, 3, 8)],
 }
 

@@ -13,13 +13,13 @@
 #pragma once
 
 #ifndef CCM_TUNE_Q
-#define CCM_TUNE_Q {0, 3, 4, 4, 4, 3, 3, 2, 2, 2, 2}
+#define CCM_TUNE_Q {0, 3, 4, 4, 4, 3, 2, 2, 2, 2, 2}
 #endif
 #ifndef CCM_TUNE_W
-#define CCM_TUNE_W {0, 6, 6, 6, 6, 6, 6, 6, 6, 6, 6}
+#define CCM_TUNE_W {0, 7, 6, 6, 6, 6, 7, 7, 6, 6, 6}
 #endif
 #ifndef CCM_TUNE_G
-#define CCM_TUNE_G {0, 16, 12, 8, 6, 6, 4, 4, 3, 3, 3}
+#define CCM_TUNE_G {0, 16, 12, 8, 6, 6, 4, 3, 4, 4, 3}
 #endif
 
 namespace ccmk {

@@ -91,6 +91,13 @@ class Oracle:
         L.oracle_ccm.argtypes = [P, P, i64, i32, i32, P, i32, i32, u64, i32,
                                  i32, P, P, P]
         L.oracle_ccm.restype = C.c_int
+        L.oracle_nested_state.argtypes = [u64, i32, i32, i32]
+        L.oracle_nested_state.restype = u64
+        L.oracle_sample_nested.argtypes = [u64, i32, i32, i32, i64, i64, P]
+        L.oracle_sample_nested.restype = C.c_int
+        L.oracle_ccm_nested.argtypes = [P, P, i64, i32, i32, P, i32, i32, u64, i32,
+                                        P, P, P]
+        L.oracle_ccm_nested.restype = C.c_int
         self.lib = L
         self.path = path
 
@@ -115,6 +122,16 @@ class Oracle:
         n = self.lib.oracle_sample_library(seed & MASK64, E, tau, L_eff, r_index,
                                            N_e, _ptr(out))
         return out[:n].copy()
+
+    def nested_state(self, seed, E, tau, r_index) -> int:
+        return int(self.lib.oracle_nested_state(seed & MASK64, E, tau, r_index))
+
+    def sample_nested(self, seed, E, tau, r_index, N_e, n_out):
+        """First n_out points of the nested ordering of (E, tau, r_index)."""
+        out = np.empty(max(n_out, 1), dtype=np.int32)
+        self._check(self.lib.oracle_sample_nested(seed & MASK64, E, tau, r_index, N_e,
+                                                  n_out, _ptr(out)))
+        return out[:n_out].copy()
 
     # -- one realization ---------------------------------------------------
     def pearson(self, a, b) -> float:
@@ -174,6 +191,19 @@ class Oracle:
         self._check(self.lib.oracle_ccm(_ptr(X), _ptr(Y), len(X), E, tau, _ptr(Ls), nL,
                                         r, seed & MASK64, excl, query_set, _ptr(rxy),
                                         _ptr(ryx), _ptr(le)))
+        return rxy, ryx, le
+
+    def ccm_nested(self, X, Y, E, tau, L, r, seed, excl=0):
+        """As ccm, with nested libraries (the first L_eff points of one ordering per r)."""
+        X, Y = _f64(X), _f64(Y)
+        Ls = np.ascontiguousarray(L, dtype=np.int64)
+        nL = len(Ls)
+        rxy = np.empty((nL, r))
+        ryx = np.empty((nL, r))
+        le = np.empty(nL, dtype=np.int64)
+        self._check(self.lib.oracle_ccm_nested(_ptr(X), _ptr(Y), len(X), E, tau, _ptr(Ls),
+                                               nL, r, seed & MASK64, excl, _ptr(rxy),
+                                               _ptr(ryx), _ptr(le)))
         return rxy, ryx, le
 
     def status_of_ccm(self, X, Y, N, E, tau, L, r, excl=0):

@@ -44,6 +44,16 @@
  *     (Steele, Lea & Flood, OOPSLA 2014); the stream for a realization is
  *     keyed by (seed, E, tau, L_eff, r_index) folded one field at a time
  *     through the SplitMix64 output mix, starting from state 0.
+ *
+ * Option of the build (not of the paper): nested libraries.  For each
+ * (E, tau, r_index) one uniformly random ordering of the embedded points is
+ * drawn and the library of size L_eff is its first L_eff points, so the
+ * libraries of one r_index grow by inclusion with L.  The ordering is the
+ * forward Fisher-Yates shuffle (Durstenfeld, CACM 7(7), 1964; Knuth's
+ * Algorithm P, TAOCP Vol. 2, Sec. 3.4.2) of 0..N_e-1, stopped after the
+ * positions needed: step k swaps position k with position
+ * k + floor(z_k (N_e - k) / 2^64), z_k the k-th output of the SplitMix64
+ * stream keyed by (seed, E, tau, r_index), folded as above.
  */
 #include <math.h>
 #include <stdint.h>
@@ -368,6 +378,92 @@ int oracle_realization(const double *S, const double *T, int64_t N, int32_t E,
     int st = oracle_neighbors(S, T, N, E, tau, lib, Le, excl, query_set,
                               NULL, NULL, NULL, rho);
     free(lib);
+    return st;
+}
+
+/* Stream of the nested ordering of (E, tau, r_index) under seed. */
+uint64_t oracle_nested_state(uint64_t seed, int32_t E, int32_t tau, int32_t r_index)
+{
+    uint64_t s = 0;
+    s = oracle_sm64_mix(s ^ seed);
+    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)E);
+    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)tau);
+    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)r_index);
+    return s;
+}
+
+/*
+ * First n_out points of the nested ordering of 0..N_e-1 (see the header):
+ * idx_out[k] for k < n_out, n_out <= N_e.
+ */
+int oracle_sample_nested(uint64_t seed, int32_t E, int32_t tau, int32_t r_index,
+                         int64_t N_e, int64_t n_out, int32_t *idx_out)
+{
+    if (!idx_out || N_e < 1 || n_out < 0 || n_out > N_e)
+        return OR_EINVAL;
+    int32_t *a = (int32_t *)malloc(sizeof(int32_t) * (size_t)N_e);
+    if (!a)
+        return OR_ENOMEM;
+    for (int64_t i = 0; i < N_e; ++i)
+        a[i] = (int32_t)i;
+    uint64_t st = oracle_nested_state(seed, E, tau, r_index);
+    for (int64_t k = 0; k < n_out; ++k) {
+        uint64_t z = oracle_sm64_next(&st);
+        unsigned __int128 prod = (unsigned __int128)z * (uint64_t)(N_e - k);
+        int64_t j = k + (int64_t)(prod >> 64);
+        int32_t t = a[k];
+        a[k] = a[j];
+        a[j] = t;
+        idx_out[k] = a[k];
+    }
+    free(a);
+    return OR_OK;
+}
+
+/*
+ * Cross-map over nested libraries for one (E, tau): as oracle_ccm, but the
+ * library of (L, r) is the first L_eff points of the nested ordering of r.
+ * Queries are every embedded point.
+ */
+int oracle_ccm_nested(const double *X, const double *Y, int64_t N, int32_t E,
+                      int32_t tau, const int64_t *L, int32_t nL, int32_t r,
+                      uint64_t seed, int32_t excl, double *rho_xy, double *rho_yx,
+                      int64_t *L_eff)
+{
+    if (!X || !Y || !L || !rho_xy || !rho_yx || N < 2 || E < 1 || E > 10 ||
+        tau < 1 || nL < 1 || r < 1)
+        return OR_EINVAL;
+    if (!valid_series(X, N) || !valid_series(Y, N))
+        return OR_EINVAL;
+    const int64_t Ne = N - (int64_t)(E - 1) * tau;
+    if (Ne < E + 2)
+        return OR_EINVAL;
+    int64_t Lmax = 0;
+    for (int32_t l = 0; l < nL; ++l) {
+        const int64_t le = L[l] < Ne ? L[l] : Ne;
+        if (L[l] < E + 2 || le < min_library(E, excl))
+            return OR_EINVAL;
+        if (le > Lmax)
+            Lmax = le;
+        if (L_eff)
+            L_eff[l] = le;
+    }
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)Lmax);
+    if (!perm)
+        return OR_ENOMEM;
+    int st = OR_OK;
+    for (int32_t q = 0; q < r && st == OR_OK; ++q) {
+        st = oracle_sample_nested(seed, E, tau, q, Ne, Lmax, perm);
+        for (int32_t l = 0; l < nL && st == OR_OK; ++l) {
+            const int64_t le = L[l] < Ne ? L[l] : Ne;
+            st = oracle_neighbors(Y, X, N, E, tau, perm, le, excl, 0, NULL, NULL, NULL,
+                                  &rho_xy[(int64_t)l * r + q]);
+            if (st == OR_OK)
+                st = oracle_neighbors(X, Y, N, E, tau, perm, le, excl, 0, NULL, NULL, NULL,
+                                      &rho_yx[(int64_t)l * r + q]);
+        }
+    }
+    free(perm);
     return st;
 }
 

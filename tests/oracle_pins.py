@@ -304,6 +304,92 @@ def pin_sampler_uniform(orc):
     assert p > 1e-4, p
 
 
+MASK64 = (1 << 64) - 1
+
+
+def _py_splitmix_mix(z):
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9 & MASK64
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EB & MASK64
+    return z ^ (z >> 31)
+
+
+def _py_nested(seed, E, tau, r_index, Ne, n):
+    """The nested ordering restated with Python integers: key folded through
+    the SplitMix64 mix, then forward Fisher-Yates steps driven by the stream."""
+    st = 0
+    for v in (seed, E, tau, r_index):
+        st = _py_splitmix_mix(st ^ (v & MASK64))
+    a = list(range(Ne))
+    out = []
+    for k in range(n):
+        st = (st + 0x9E3779B97F4A7C15) & MASK64
+        z = _py_splitmix_mix(st)
+        j = k + ((z * (Ne - k)) >> 64)
+        a[k], a[j] = a[j], a[k]
+        out.append(a[k])
+    return out
+
+
+def pin_nested_structure(orc):
+    """Nested ordering: distinct points in range, a permutation when complete,
+    shorter draws are prefixes of longer ones, every key field matters, and
+    the points match an independent statement of the shuffle."""
+    for Ne, n in ((10, 3), (100, 37), (1000, 999), (57, 57)):
+        idx = orc.sample_nested(5, 2, 1, 0, Ne, n)
+        assert len(idx) == n and len(set(idx.tolist())) == n
+        assert idx.min() >= 0 and idx.max() < Ne
+    full = orc.sample_nested(9, 3, 2, 4, 400, 400)
+    assert np.array_equal(np.sort(full), np.arange(400))
+    for n1, n2 in ((1, 50), (17, 400), (399, 400)):
+        assert np.array_equal(orc.sample_nested(9, 3, 2, 4, 400, n1),
+                              orc.sample_nested(9, 3, 2, 4, 400, n2)[:n1])
+    base = orc.sample_nested(1, 2, 3, 4, 500, 50)
+    for args in ((2, 2, 3, 4), (1, 3, 3, 4), (1, 2, 4, 4), (1, 2, 3, 5), (1, 3, 2, 4)):
+        assert not np.array_equal(orc.sample_nested(*args, 500, 50), base), args
+    for key in ((1, 2, 3, 4, 500, 50), (12345678901234, 10, 5, 249, 9955, 200),
+                (7, 1, 1, 0, 3, 3)):
+        assert orc.sample_nested(*key).tolist() == _py_nested(*key), key
+
+
+def pin_nested_uniform(orc):
+    """Nested ordering is uniform: first point, first-4 inclusions and the
+    ordered first pair all pass chi^2."""
+    Ne, R = 12, 6600
+    first = np.zeros(Ne)
+    incl = np.zeros(Ne)
+    pairs = np.zeros((Ne, Ne))
+    for q in range(R):
+        idx = orc.sample_nested(31, 2, 1, q, Ne, 4)
+        first[idx[0]] += 1
+        incl[idx] += 1
+        pairs[idx[0], idx[1]] += 1
+    assert stats.chisquare(first).pvalue > 1e-4
+    assert stats.chisquare(incl).pvalue > 1e-4
+    off = pairs[~np.eye(Ne, dtype=bool)]
+    assert pairs.trace() == 0
+    assert stats.chisquare(off).pvalue > 1e-4
+
+
+def pin_nested_ccm(orc):
+    """Nested cross map: each (L, r) is the realization over the first L_eff
+    points of r's ordering; the libraries of one r are nested; the full
+    library gives the same rho as the independent draws."""
+    x, y = synth.coupled_logistic(260)
+    E, tau, L, r, seed = 2, 1, [20, 75, 259, 300], 3, 17
+    ne = 260 - (E - 1) * tau
+    rxy, ryx, le = orc.ccm_nested(x, y, E, tau, L, r, seed)
+    assert le.tolist() == [20, 75, 259, 259]
+    for q in range(r):
+        perm = orc.sample_nested(seed, E, tau, q, ne, 259)
+        for il, l in enumerate(le):
+            lib = np.sort(perm[:l])
+            assert rxy[il, q] == orc.neighbors(y, x, E, tau, lib)[3]
+            assert ryx[il, q] == orc.neighbors(x, y, E, tau, lib)[3]
+        assert set(perm[:20].tolist()) <= set(perm[:75].tolist())
+    ixy, iyx, _ = orc.ccm(x, y, E, tau, [259], r, seed)
+    assert np.array_equal(rxy[2], ixy[0]) and np.array_equal(ryx[3], iyx[0])
+
+
 def pin_input_rules(orc):
     """Invalid inputs are refused; L above N_e is clamped, not refused."""
     x = np.linspace(0.1, 0.9, 50)
@@ -337,5 +423,8 @@ ALL_PINS = [
     pin_splitmix64_known_answers,
     pin_sampler_structure,
     pin_sampler_uniform,
+    pin_nested_structure,
+    pin_nested_uniform,
+    pin_nested_ccm,
     pin_input_rules,
 ]

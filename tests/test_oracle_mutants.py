@@ -36,7 +36,16 @@ MUTANTS = [
     ("pearson without sqrt", "return sab / sqrt(saa * sbb);", "return sab / (saa * sbb);"),
     ("pearson mean over n-1", "ma /= (double)n;", "ma /= (double)(n - 1);"),
     ("sampler off by one", "if (u < (uint64_t)(L_eff - s))", "if (u <= (uint64_t)(L_eff - s))"),
-    ("sampler key drops tau", "    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)tau);\n", ""),
+    ("sampler key drops tau",
+     "    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)tau);\n    s = oracle_sm64_mix(s ^ (uint64_t)L_eff);",
+     "    s = oracle_sm64_mix(s ^ (uint64_t)L_eff);"),
+    ("nested shuffle range one short", "(unsigned __int128)z * (uint64_t)(N_e - k);",
+     "(unsigned __int128)z * (uint64_t)(N_e - k - 1);"),
+    ("nested key drops r",
+     "    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)r_index);\n    return s;\n}\n\n/*\n * First n_out",
+     "    return s;\n}\n\n/*\n * First n_out"),
+    ("nested library is a suffix", "st = oracle_neighbors(Y, X, N, E, tau, perm, le,",
+     "st = oracle_neighbors(Y, X, N, E, tau, perm + (Lmax - le), le,"),
     ("splitmix constant", "0xbf58476d1ce4e5b9ULL", "0xbf58476d1ce4e5b8ULL"),
     ("clamp one short", "const int64_t Le = L < Ne ? L : Ne;",
      "const int64_t Le = L < Ne ? L : Ne - 1;"),

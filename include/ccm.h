@@ -104,6 +104,19 @@ typedef struct {
    per table.  Not supported by the served form (ignored there). */
 #define CCM_FLAG_TABLE 8u
 #define CCM_TABLE_WIDTH 1024
+/* Nested libraries (an option of this library, not of the paper): the
+   library of (E, tau, L, r) is the first L_eff points of one uniformly
+   random ordering of the embedded points per (E, tau, r) -- a forward
+   Fisher-Yates shuffle driven by the SplitMix64 stream keyed by
+   (seed, E, tau, r) -- so the libraries of one r grow by inclusion with L.
+   Each query then scans the largest library once, in segments, taking its
+   E+1 neighbours at every library size: the cross map costs
+   N_e * max(L_eff) pairs per (E, tau, r, direction) instead of
+   N_e * sum(L_eff).  The rho values differ from the default draws (the
+   libraries are correlated across L).  ccm and ccm_sweep (and their device
+   forms) only, with query_set 0; not with CCM_FLAG_TABLE or CCM_FLAG_PLAIN
+   (CCM_E_INVAL). */
+#define CCM_FLAG_NESTED 16u
 
 /* Create a context on HIP device `device`.  *out receives the handle. */
 ccm_status ccm_create(int device, ccm_ctx **out);
@@ -250,6 +263,16 @@ void ccm_server_destroy(ccm_server *srv);
 ccm_status ccm_library(ccm_ctx *ctx, int64_t N_e, int32_t E, int32_t tau,
                        int64_t L_eff, int32_t r_index, uint64_t seed,
                        int32_t *idx_out);
+
+/*
+ * Test hook: the first n_out points of the nested ordering that
+ * CCM_FLAG_NESTED draws for realization r_index of (E, tau) under seed, over
+ * N_e embedded points (the library of size L_eff is its first L_eff points).
+ *   idx_out     host int32[n_out], in drawing order; 1 <= n_out <= N_e
+ */
+ccm_status ccm_nested_library(ccm_ctx *ctx, int64_t N_e, int32_t E, int32_t tau,
+                              int32_t r_index, uint64_t seed, int64_t n_out,
+                              int32_t *idx_out);
 
 /*
  * Test hook: one realization over a caller-given library (Section 3.2 and

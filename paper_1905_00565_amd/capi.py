@@ -31,13 +31,14 @@ CCM_FLAG_PLAIN = 1
 CCM_FLAG_NO_GRAPH = 2
 CCM_FLAG_PERSISTENT = 4
 CCM_FLAG_TABLE = 8
+CCM_FLAG_NESTED = 16
 CCM_TABLE_WIDTH = 1024
 
 # Every symbol include/ccm.h declares (checked by the ABI test).
 EXPORTS = [
     "ccm_create", "ccm_destroy", "ccm_last_error", "ccm", "ccm_sweep",
     "ccm_matrix", "ccm_dev", "ccm_sweep_dev", "ccm_matrix_dev", "ccm_library",
-    "ccm_neighbors",
+    "ccm_nested_library", "ccm_neighbors",
     "ccm_profile_enable", "ccm_profile_read",
     "ccm_server_create", "ccm_submit", "ccm_wait", "ccm_result", "ccm_cancel",
     "ccm_server_destroy",
@@ -272,6 +273,15 @@ def ccm_library(ctx, N_e, E, tau, L_eff, r_index, seed):
     return out[:L_eff]
 
 
+def ccm_nested_library(ctx, N_e, E, tau, r_index, seed, n_out):
+    """First n_out points of the nested ordering of (E, tau, r_index)."""
+    out = np.empty(n_out, dtype=np.int32)
+    _check(ctx, lib().ccm_nested_library(ctx, C.c_int64(N_e), E, tau, r_index,
+                                         C.c_uint64(seed & (2**64 - 1)), C.c_int64(n_out),
+                                         _ptr(out)))
+    return out
+
+
 def ccm_neighbors(ctx, lib_series, target, E, tau, lib_idx, exclusion_radius=0,
                   query_set=0, flags=0):
     """(nbr [Nq][E+1], d2 [Nq][E+1] float32, pred [Nq], rho) of one library."""
@@ -419,6 +429,9 @@ class Context:
 
     def ccm_library(self, *a, **k):
         return ccm_library(self.handle, *a, **k)
+
+    def ccm_nested_library(self, *a, **k):
+        return ccm_nested_library(self.handle, *a, **k)
 
     def ccm_neighbors(self, *a, **k):
         return ccm_neighbors(self.handle, *a, **k)

@@ -20,6 +20,7 @@ struct Exec {
   DevBuf d_orders;
   DevBuf d_tt;       // causal matrix: targets time-major [N][target_stride(M)]
   DevBuf d_tables, d_table;   // distance indexing table jobs and rows
+  DevBuf d_nested, d_scratch, d_segs, d_rz_fin;   // nested libraries
   std::vector<int64_t> plain_first;   // per realization: first plain item
   hipGraphExec_t graph = nullptr;
   ~Exec() {

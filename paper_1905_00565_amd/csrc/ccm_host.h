@@ -147,6 +147,13 @@ struct Plan {
   int te_max_ne[kMaxE + 1] = {0};     // largest table of E (launch grid)
   int e_table_ne[kMaxE + 1] = {0};    // largest n_e walked by E's items (launch LDS)
   int64_t table_rz = 0;               // realizations that walk a table
+  // nested libraries (CCM_FLAG_NESTED): rz holds chains, rz_fin one record
+  // per rho (slot range of its segment, output index)
+  std::vector<NestedJob> nested;
+  int64_t n_scratch = 0;              // int32 shuffle positions
+  std::vector<int32_t> segs;          // segment bounds of every chain
+  std::vector<Realization> rz_fin;
+  int64_t n_rho = 0;                  // rho values produced
 };
 
 // Whether a realization walks a distance indexing table, and the offset of

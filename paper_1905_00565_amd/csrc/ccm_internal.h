@@ -104,6 +104,22 @@ struct Realization {
   int64_t out_index; // where rho goes in the caller's output
   int64_t table_off; // int32: distance-index rows of the embedding, or -1 (brute force)
   int32_t table_w;   // entries per table row (min(CCM_TABLE_WIDTH, n_e))
+  int32_t n_seg;     // nested libraries: segments (library sizes) of this chain, else 0
+  int64_t seg_off;   // int32: n_seg + 1 segment bounds (nested libraries)
+};
+
+// One nested ordering: the first n_out points of a forward Fisher-Yates
+// shuffle of 0..n_e-1 (stream keyed by (seed, E, tau, r_index)), written to
+// out; scratch holds the n_e positions being shuffled.
+struct NestedJob {
+  uint64_t seed;
+  int64_t n_e;
+  int64_t n_out;
+  int64_t out_off;      // int32 into the library pool
+  int64_t scratch_off;  // int32 into the shuffle scratch
+  int32_t E;
+  int32_t tau;
+  int32_t r_index;
   int32_t pad;
 };
 
@@ -171,6 +187,18 @@ hipError_t launch_table_build(int E, const TableJob* jobs, int n_jobs, int max_n
 constexpr int kTableWidth = 1024;           // CCM_TABLE_WIDTH
 constexpr int kTableMaxNe = 131072;         // largest embedding given a table (LDS bitmask)
 constexpr int table_row_stride(int w) { return (w + 3) & ~3; }
+// Nested libraries: the shuffles (one workgroup per job), and the cross map
+// of chains (one realization per (E, tau, r, direction) holding every
+// library size as a segment; partial slot of segment k, tile t:
+// slot_base + k * n_tiles + t; scan starts likewise, kWaves per slot).
+hipError_t launch_sample_nested(const NestedJob* jobs, int64_t n_jobs, int32_t* scratch,
+                                int32_t* out_pool, hipStream_t st);
+hipError_t launch_crossmap_nested(int E, int mode, int grid, const Realization* rzs,
+                                  const Item* items, int n_items, int* next,
+                                  const float* emb, const float* pts, const int32_t* pj,
+                                  const int32_t* qord, const int32_t* start, const double* tgt,
+                                  const int32_t* seg, Moments* partial, int window,
+                                  hipStream_t st);
 hipError_t launch_finalize(const Realization* rzs, int64_t n_rz,
                            const Moments* partial, double* out, hipStream_t st);
 

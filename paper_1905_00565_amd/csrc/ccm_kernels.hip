@@ -231,6 +231,37 @@ __global__ void k_sample(const SampleJob* __restrict__ jobs, int64_t n_jobs,
   for (; s < J.l_eff; ++s, ++j) out[s] = (int32_t)j;
 }
 
+// Nested libraries (an option of this library): the first n_out points of
+// the forward Fisher-Yates shuffle (Durstenfeld 1964; Knuth's Algorithm P,
+// TAOCP Vol. 2, Sec. 3.4.2) of 0..n_e-1: step k swaps position k with
+// position k + floor(z_k (n_e - k) / 2^64), z_k the k-th SplitMix64 output
+// of the stream keyed by (seed, E, tau, r).  One workgroup per job: the
+// positions are set to the identity in parallel, then one lane shuffles.
+__global__ __launch_bounds__(kBlock) void k_sample_nested(const NestedJob* __restrict__ jobs,
+                                                          int32_t* __restrict__ scratch,
+                                                          int32_t* __restrict__ out_pool) {
+  const NestedJob J = jobs[blockIdx.x];
+  int32_t* __restrict__ a = scratch + J.scratch_off;
+  for (int64_t i = threadIdx.x; i < J.n_e; i += kBlock) a[i] = (int32_t)i;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  uint64_t st = 0;
+  st = sm_mix(st ^ J.seed);
+  st = sm_mix(st ^ (uint64_t)(int64_t)J.E);
+  st = sm_mix(st ^ (uint64_t)(int64_t)J.tau);
+  st = sm_mix(st ^ (uint64_t)(int64_t)J.r_index);
+  int32_t* __restrict__ out = out_pool + J.out_off;
+  for (int64_t k = 0; k < J.n_out; ++k) {
+    st += 0x9e3779b97f4a7c15ull;
+    const uint64_t z = sm_mix(st);
+    const int64_t j = k + (int64_t)__umul64hi(z, (uint64_t)(J.n_e - k));
+    const int32_t t = a[k];
+    a[k] = a[j];
+    a[j] = t;
+    out[k] = a[k];
+  }
+}
+
 // The library of one realization, laid out contiguously in visiting order
 // (coordinates AoS and embedded indices), so the scan
 // streams it through the scalar cache with no dependent index load.  For each
@@ -593,30 +624,20 @@ __device__ __forceinline__ void table_bitmask(const Realization& R,
   __syncthreads();
 }
 
-template <int E, int Q, int MODE, bool TBL>
-__device__ __forceinline__ void scan_library(
-    const Realization& R, int tile, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    int query_set, int window, const TableArgs& ta, uint32_t* tlds,
-    ScanState<E, Q, MODE>& S) {
+// Queries of this lane for item (R, tile): positions tile*QT + wave*QW +
+// m*64 + lane of the query order (every embedded point, or the ordered
+// library itself), so that each wavefront holds a run of QW consecutive
+// queries.  Their lists start empty.  Returns whether the lane's wavefront
+// has any query (uniform across the wavefront).
+template <int E, int Q, int MODE>
+__device__ __forceinline__ bool scan_queries(const Realization& R, int tile, int wave, int lane,
+                                             const float* __restrict__ emb,
+                                             const int32_t* __restrict__ pj,
+                                             const int32_t* __restrict__ qord, int query_set,
+                                             ScanState<E, Q, MODE>& S) {
   constexpr int KS = Slots<E, MODE>::KS;
-  constexpr int G = Group<E>::G;
-  constexpr int QT = kBlock * Q;                    // queries per tile
-  constexpr int QW = 64 * Q;                        // queries per wavefront
-  // the wavefront index is uniform: say so, so that the scan position and
-  // the library addresses stay scalar
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const float* __restrict__ emb = emb_pool + R.emb_off;
-  const float* __restrict__ pts = pts_pool + R.pts_off;
-  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
-  const int32_t* __restrict__ qord = qord_pool + R.qord_off;
-  const int L = R.l_eff;
-
-  // queries of this lane: positions tile*QT + wave*QW + m*64 + lane of the
-  // query order (every embedded point, or the ordered library itself), so
-  // that each wavefront holds a run of QW consecutive queries
+  constexpr int QT = kBlock * Q;
+  constexpr int QW = 64 * Q;
   bool any = false;
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
@@ -632,30 +653,19 @@ __device__ __forceinline__ void scan_library(
   for (int m = 0; m < Q; ++m)
 #pragma unroll
     for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
+  return __builtin_amdgcn_ballot_w64(any) != 0;
+}
 
-  // A wavefront with no query (the tail of the last tile) has nothing to scan.
-  if (!__builtin_amdgcn_ballot_w64(any)) return;
-
-  // Table walk (the realization's rows exist): done unless a row ran short.
-  // Compiled only into the launches that carry tables.
-  if constexpr (TBL) {
-    if (R.table_off >= 0 && ta.words > 0) {
-      if (walk_table<E, Q, MODE>(R, ta.pool, tlds, reinterpret_cast<int32_t*>(tlds + ta.words),
-                                 emb, window, S))
-        return;
-#pragma unroll
-      for (int m = 0; m < Q; ++m)
-#pragma unroll
-        for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
-    }
-  }
-
-  // Brute-force scan of every library position, outward from the
-  // wavefront's start s0: a forward group [f, f+G) and a backward group
-  // [b-G, b) per step while both fit, then the remaining groups of the
-  // longer side, then single positions at both ends.
-  int s0 = query_set ? min(tile * QT + wave * QW + QW / 2, L - 1)
-                     : start_pool[(R.slot_base + tile) * kWaves + wave];
+// Brute-force scan of the library positions [0, L) (coordinates pts AoS,
+// indices pj), outward from s0: a forward group [f, f+G) and a backward
+// group [b-G, b) per step while both fit, then the remaining groups of the
+// longer side, then single positions at both ends.  Every position is
+// visited once; the lists keep the first E+1 candidates in (d2, j) order.
+template <int E, int Q, int MODE>
+__device__ __forceinline__ void scan_range(const float* __restrict__ pts,
+                                           const int32_t* __restrict__ pj, int L, int s0,
+                                           int window, ScanState<E, Q, MODE>& S) {
+  constexpr int G = Group<E>::G;
   s0 = min(max(s0, 0), L);
   int f = s0, b = s0;
   const int both = min((L - s0) / G, s0 / G);
@@ -685,6 +695,48 @@ __device__ __forceinline__ void scan_library(
   for (; b - G >= 0; b -= G) scan_group<E, Q, MODE, G>(pts, pj, b - G, S.qc, S.qi, window, S.key);
   for (; f < L; ++f) scan_group<E, Q, MODE, 1>(pts, pj, f, S.qc, S.qi, window, S.key);
   for (; b > 0; --b) scan_group<E, Q, MODE, 1>(pts, pj, b - 1, S.qc, S.qi, window, S.key);
+}
+
+template <int E, int Q, int MODE, bool TBL>
+__device__ __forceinline__ void scan_library(
+    const Realization& R, int tile, const float* __restrict__ emb_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
+    int query_set, int window, const TableArgs& ta, uint32_t* tlds,
+    ScanState<E, Q, MODE>& S) {
+  constexpr int KS = Slots<E, MODE>::KS;
+  constexpr int QT = kBlock * Q;                    // queries per tile
+  constexpr int QW = 64 * Q;                        // queries per wavefront
+  // the wavefront index is uniform: say so, so that the scan position and
+  // the library addresses stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const float* __restrict__ emb = emb_pool + R.emb_off;
+  const float* __restrict__ pts = pts_pool + R.pts_off;
+  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
+  const int32_t* __restrict__ qord = qord_pool + R.qord_off;
+  const int L = R.l_eff;
+
+  // A wavefront with no query (the tail of the last tile) has nothing to scan.
+  if (!scan_queries<E, Q, MODE>(R, tile, wave, lane, emb, pj, qord, query_set, S)) return;
+
+  // Table walk (the realization's rows exist): done unless a row ran short.
+  // Compiled only into the launches that carry tables.
+  if constexpr (TBL) {
+    if (R.table_off >= 0 && ta.words > 0) {
+      if (walk_table<E, Q, MODE>(R, ta.pool, tlds, reinterpret_cast<int32_t*>(tlds + ta.words),
+                                 emb, window, S))
+        return;
+#pragma unroll
+      for (int m = 0; m < Q; ++m)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
+    }
+  }
+
+  const int s0 = query_set ? min(tile * QT + wave * QW + QW / 2, L - 1)
+                           : start_pool[(R.slot_base + tile) * kWaves + wave];
+  scan_range<E, Q, MODE>(pts, pj, L, s0, window, S);
 }
 
 // The E+1 neighbours of query m (nearest first): its running list.  Every
@@ -1071,6 +1123,70 @@ __global__ __launch_bounds__(kBlock) void k_table_build(const TableJob* __restri
   for (int x = tid; x < rs; x += kBlock) row[x] = x < w ? (int32_t)(keys[x] & 0xffffffffu) : -1;
 }
 
+// ---------------------------------------------------------------------------
+// nested libraries: one scan per chain, a snapshot per library size
+// ---------------------------------------------------------------------------
+//
+// A chain holds the libraries of one (E, tau, r, direction): the prefixes of
+// one ordering, split into segments at the library sizes (segment k holds
+// the points between sizes k-1 and k, gathered in visiting order with its
+// own scan starts).  The running lists after segments 0..k are exactly the
+// first E+1 candidates of the library of size k (a list only ever keeps the
+// smallest keys seen), so after each segment every query predicts from them
+// and the tile's moments for that size are merged and stored.
+template <int E, int Q, int MODE>
+__device__ __forceinline__ void nested_item(
+    const Realization& R, int tile, const float* __restrict__ emb_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
+    const double* __restrict__ tgt_pool, const int32_t* __restrict__ seg_pool,
+    Moments* __restrict__ partial, int window, Moments* red) {
+  constexpr int K = E + 1;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const float* __restrict__ emb = emb_pool + R.emb_off;
+  const float* __restrict__ pts = pts_pool + R.pts_off;
+  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
+  const int32_t* __restrict__ qord = qord_pool + R.qord_off;
+  const double* __restrict__ tgt = tgt_pool + R.tgt_off;
+  const int32_t* __restrict__ seg = seg_pool + R.seg_off;
+  const int64_t off = (int64_t)(E - 1) * R.tau;
+
+  ScanState<E, Q, MODE> S;
+  const bool any = scan_queries<E, Q, MODE>(R, tile, wave, lane, emb, pj, qord, 0, S);
+  for (int k = 0; k < R.n_seg; ++k) {
+    const int b0 = seg[k], b1 = seg[k + 1];
+    const int64_t slot = R.slot_base + (int64_t)k * R.n_tiles + tile;
+    if (any)
+      scan_range<E, Q, MODE>(pts + (int64_t)b0 * E, pj + b0, b1 - b0,
+                             start_pool[slot * kWaves + wave], window, S);
+    Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      if (S.qi[m] < 0) continue;
+      float nd[K];
+      int32_t nj[K];
+      select_neighbors<E, Q, MODE>(S, m, nd, nj);
+      double w[K];
+      simplex_weights<K>(nd, w);
+      double pred = 0.0;
+#pragma unroll
+      for (int t = 0; t < K; ++t) pred += w[t] * tgt[nj[t] + off];
+      mom_add(mo, tgt[S.qi[m] + off], pred);
+    }
+    red[tid] = mo;
+    __syncthreads();
+#pragma unroll
+    for (int s2 = kBlock / 2; s2 > 0; s2 >>= 1) {
+      if (tid < s2) red[tid] = mom_merge(red[tid], red[tid + s2]);
+      __syncthreads();
+    }
+    if (tid == 0) partial[slot] = red[0];
+    __syncthreads();
+  }
+}
+
 // Work items are taken in list order (the host lists them longest first).
 // With next == nullptr each workgroup takes items blockIdx.x, +gridDim.x, ...;
 // otherwise workgroups pull the next item from an atomic counter that starts
@@ -1156,6 +1272,34 @@ __global__ __launch_bounds__(kBlock) void k_crossmap_multi(
 
 // rho[self][b] of every realization from the per-tile sums; NaN on the
 // diagonal and when either side is constant.
+template <int E, int Q, int MODE>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(kTuneW[E] > 0 ? kTuneW[E] : 1, 8))) void k_crossmap_nested(
+    const Realization* __restrict__ rzs, const Item* __restrict__ items,
+    int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
+    const double* __restrict__ tgt_pool, const int32_t* __restrict__ seg_pool,
+    Moments* __restrict__ partial, int window) {
+  __shared__ Moments red[kBlock];
+  __shared__ int s_next;
+  int it = xcd_item(blockIdx.x, gridDim.x);
+  while (it < n_items) {
+    const Item I = items[it];
+    const Realization R = rzs[I.rz];
+    nested_item<E, Q, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
+                            tgt_pool, seg_pool, partial, window, red);
+    if (next == nullptr) {
+      it += gridDim.x;
+    } else {
+      if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(next, 1);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(s_next);
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void k_finalize_multi(const Realization* __restrict__ rzs,
                                  const int32_t* __restrict__ self_of, int64_t n_rz,
                                  int m_series, const Sums* __restrict__ partial,
@@ -1369,6 +1513,58 @@ hipError_t launch_table_build(int E, const TableJob* jobs, int n_jobs, int max_n
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_sample_nested(const NestedJob* jobs, int64_t n_jobs, int32_t* scratch,
+                                int32_t* out_pool, hipStream_t st) {
+  if (n_jobs <= 0) return hipSuccess;
+  k_sample_nested<<<(unsigned)n_jobs, kBlock, 0, st>>>(jobs, scratch, out_pool);
+  return hipGetLastError();
+}
+
+template <int E>
+static hipError_t launch_nested_e(int mode, int grid, const Realization* rzs,
+                                  const Item* items, int n_items, int* next,
+                                  const float* emb, const float* pts, const int32_t* pj,
+                                  const int32_t* qord, const int32_t* start, const double* tgt,
+                                  const int32_t* seg, Moments* partial, int window,
+                                  hipStream_t st) {
+  constexpr int Q = DefaultQ<E>::Q;
+  switch (mode) {
+    case kExclSelf:
+      k_crossmap_nested<E, Q, kExclSelf><<<grid, kBlock, 0, st>>>(
+          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, seg, partial, window);
+      break;
+    case kKeepSelf:
+      k_crossmap_nested<E, Q, kKeepSelf><<<grid, kBlock, 0, st>>>(
+          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, seg, partial, window);
+      break;
+    default:
+      k_crossmap_nested<E, Q, kWindow><<<grid, kBlock, 0, st>>>(
+          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, seg, partial, window);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_crossmap_nested(int E, int mode, int grid, const Realization* rzs,
+                                  const Item* items, int n_items, int* next,
+                                  const float* emb, const float* pts, const int32_t* pj,
+                                  const int32_t* qord, const int32_t* start, const double* tgt,
+                                  const int32_t* seg, Moments* partial, int window,
+                                  hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  switch (E) {
+#define CCM_NCASE(e)                                                                   \
+  case e:                                                                              \
+    return launch_nested_e<e>(mode, grid, rzs, items, n_items, next, emb, pts, pj, qord, \
+                              start, tgt, seg, partial, window, st);
+    CCM_NCASE(1) CCM_NCASE(2) CCM_NCASE(3) CCM_NCASE(4) CCM_NCASE(5)
+    CCM_NCASE(6) CCM_NCASE(7) CCM_NCASE(8) CCM_NCASE(9) CCM_NCASE(10)
+#undef CCM_NCASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_crossmap(int E, int mode, bool dump, int grid,

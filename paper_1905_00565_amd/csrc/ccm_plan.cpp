@@ -75,6 +75,147 @@ static void order_items(Plan& p) {
   if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
 }
 
+// Nested libraries: per (E, tau) the distinct library sizes, sorted, split
+// one ordering per r into segments; per (r, direction) one chain whose
+// segments are gathered separately (each in visiting order, with its own
+// scan starts) and scanned in order, one snapshot per size.
+static Plan make_plan_nested(const Spec& s) {
+  if (s.query_set != 0) fail(CCM_E_INVAL, "nested libraries predict every embedded point");
+  if (s.flags & (CCM_FLAG_TABLE | CCM_FLAG_PLAIN))
+    fail(CCM_E_INVAL, "nested libraries do not combine with the table or plain forms");
+  Plan p;
+  p.spec = s;
+  p.mode = excl_mode(s.excl);
+  p.window = s.excl > 0 ? s.excl : 0;
+  const int nE = (int)s.E.size(), nT = (int)s.tau.size(), nL = (int)s.L.size();
+  const int64_t N = s.N;
+  p.n64 = 2 * N;
+  p.n32 = 2 * N;
+  p.ingest.push_back({0, 0, 2 * N});
+  const int64_t sorted_limit = gather_max_sorted_n_e();
+  p.n_out = 2LL * nE * nT * nL * s.r;
+  p.L_eff.assign((size_t)nE * nT * nL, 0);
+  for (int ie = 0; ie < nE; ++ie) {
+    const int32_t E = s.E[ie];
+    const int Q = crossmap_queries_per_lane(E, false);
+    const int64_t qt = (int64_t)kBlock * Q;
+    for (int it = 0; it < nT; ++it) {
+      const int32_t tau = s.tau[it];
+      const int64_t ne = N - (int64_t)(E - 1) * tau;
+      std::vector<int64_t> sizes;
+      for (int il = 0; il < nL; ++il) {
+        const int64_t le = std::min(s.L[il], ne);
+        p.L_eff[((size_t)ie * nT + it) * nL + il] = le;
+        sizes.push_back(le);
+      }
+      std::sort(sizes.begin(), sizes.end());
+      sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+      const int n_seg = (int)sizes.size();
+      const int64_t lmax = sizes.back();
+      const int64_t seg_off = (int64_t)p.segs.size();
+      p.segs.push_back(0);
+      for (int64_t z : sizes) p.segs.push_back((int32_t)z);
+      int64_t emb_off[2], qord_off[2], ord_off[2];
+      for (int sr = 0; sr < 2; ++sr) {
+        emb_off[sr] = p.n_emb;
+        qord_off[sr] = p.n_qord;
+        ord_off[sr] = order_set(p, sr, E == 1 ? 0 : tau);
+        p.embed.push_back({sr * N, p.n_emb, ord_off[sr], p.n_qord, ne, N, E, tau});
+        p.n_emb += ne * E;
+        p.n_qord += ne;
+        p.max_embed = std::max(p.max_embed, ne * E);
+      }
+      const int32_t sorted = ne <= sorted_limit ? 1 : 0;
+      if (sorted) p.max_sorted_n_e = std::max(p.max_sorted_n_e, ne);
+      for (int ri = 0; ri < s.r; ++ri) {
+        NestedJob nj{};
+        nj.seed = s.seed;
+        nj.n_e = ne;
+        nj.n_out = lmax;
+        nj.out_off = p.n_lib;
+        nj.scratch_off = p.n_scratch;
+        nj.E = E;
+        nj.tau = tau;
+        nj.r_index = ri;
+        p.nested.push_back(nj);
+        p.n_lib += lmax;
+        p.n_scratch += ne;
+        for (int dir = 0; dir < 2; ++dir) {
+          const int lib_s = dir == 0 ? 1 : 0;
+          const int tgt_s = dir == 0 ? 0 : 1;
+          Realization R{};
+          R.emb_off = emb_off[lib_s];
+          R.pts_off = p.n_pts;
+          R.pj_off = p.n_pj;
+          R.qord_off = qord_off[lib_s];
+          R.tgt_off = tgt_s * N;
+          R.E = E;
+          R.tau = tau;
+          R.n_e = (int32_t)ne;
+          R.l_eff = (int32_t)lmax;
+          R.n_query = (int32_t)ne;
+          R.n_tiles = (int32_t)((ne + qt - 1) / qt);
+          R.slot_base = p.n_slots;
+          R.out_index = -1;
+          R.table_off = -1;
+          R.n_seg = n_seg;
+          R.seg_off = seg_off;
+          for (int k = 0; k < n_seg; ++k) {
+            const int64_t b0 = p.segs[seg_off + k], b1 = p.segs[seg_off + k + 1];
+            GatherJob gj{};
+            gj.emb_off = R.emb_off;
+            gj.lib_off = nj.out_off + b0;
+            gj.order_off = ord_off[lib_s];
+            gj.pts_off = R.pts_off + b0 * E;
+            gj.pj_off = R.pj_off + b0;
+            gj.start_off = (R.slot_base + (int64_t)k * R.n_tiles) * kWaves;
+            gj.l_eff = b1 - b0;
+            gj.n_e = ne;
+            gj.n_series = N;
+            gj.E = E;
+            gj.tau = tau;
+            gj.qt = (int32_t)qt;
+            gj.query_set = 0;
+            gj.sorted = sorted;
+            p.gather.push_back(gj);
+          }
+          for (int il = 0; il < nL; ++il) {
+            const int64_t le = p.L_eff[((size_t)ie * nT + it) * nL + il];
+            const int k = (int)(std::lower_bound(sizes.begin(), sizes.end(), le) - sizes.begin());
+            Realization F{};
+            F.slot_base = R.slot_base + (int64_t)k * R.n_tiles;
+            F.n_tiles = R.n_tiles;
+            F.out_index = ((((int64_t)dir * nE + ie) * nT + it) * nL + il) * s.r + ri;
+            p.rz_fin.push_back(F);
+            p.preds += (double)ne;
+          }
+          p.n_pts += lmax * E;
+          p.n_pj += lmax;
+          p.n_slots += (int64_t)R.n_tiles * n_seg;
+          p.rz.push_back(R);
+          double pairs = (double)ne * (double)lmax;
+          if (p.mode == kExclSelf) pairs -= (double)lmax;
+          p.pairs += pairs;
+          p.flops += pairs * (3.0 * E - 1.0);
+        }
+      }
+    }
+  }
+  p.n_rho = (int64_t)p.rz_fin.size();
+  if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
+  order_items(p);
+  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
+                     p.n_sets, nullptr, nullptr));
+  p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
+                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
+                   (size_t)p.n_ord * 16 + p.n_scratch * 4 + p.segs.size() * 4 +
+                   p.n_slots * sizeof(Moments) + p.n_out * 8 +
+                   (p.rz.size() + p.rz_fin.size()) * sizeof(Realization) +
+                   p.items.size() * sizeof(Item) + p.nested.size() * sizeof(NestedJob) +
+                   p.gather.size() * sizeof(GatherJob);
+  return p;
+}
+
 // Validate a sweep and lay out every realization of it.
 Plan make_plan(const Spec& s) {
   if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
@@ -96,6 +237,7 @@ Plan make_plan(const Spec& s) {
           fail(CCM_E_INVAL, "library too small for the exclusion window");
       }
     }
+  if (s.flags & CCM_FLAG_NESTED) return make_plan_nested(s);
 
   Plan p;
   p.spec = s;
@@ -195,6 +337,7 @@ Plan make_plan(const Spec& s) {
     }
   }
   if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
+  p.n_rho = (int64_t)p.rz.size();
 
   order_items(p);
 
@@ -213,6 +356,8 @@ Plan make_plan(const Spec& s) {
 // series; one realization per (searched series, L, r) predicting all others.
 Plan make_plan_matrix(const Spec& s) {
   if (s.M < 2) fail(CCM_E_INVAL, "M must be >= 2");
+  if (s.flags & CCM_FLAG_NESTED)
+    fail(CCM_E_INVAL, "nested libraries are not supported by the matrix form");
   if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
   if (s.L.empty()) fail(CCM_E_INVAL, "empty L list");
   if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
@@ -317,6 +462,7 @@ Plan make_plan_matrix(const Spec& s) {
         p.flops += pairs * (3.0 * E - 1.0);
         p.preds += nq * (M - 1);
       }
+  p.n_rho = (int64_t)p.rz.size() * (M - 1);
   order_items(p);
   HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
                      p.n_sets, nullptr, nullptr));

@@ -77,6 +77,12 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
     upload(ex->d_tables, p.tables);
     ex->d_table.ensure(p.n_table * 4);
   }
+  if (!p.nested.empty()) {
+    upload(ex->d_nested, p.nested);
+    ex->d_scratch.ensure(p.n_scratch * 4);
+    upload(ex->d_segs, p.segs);
+    upload(ex->d_rz_fin, p.rz_fin);
+  }
   ex->d_s64.ensure(p.n64 * 8);
   ex->d_s32.ensure(p.n32 * 4);
   ex->d_iota.ensure(p.n_ord * 4);
@@ -139,9 +145,14 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
     HIPCHK(launch_table_build(E, ex->d_tables.as<TableJob>() + p.te_first[E], p.te_count[E],
                               p.te_max_ne[E], ex->d_emb.as<float>(), ex->d_table.as<int32_t>(),
                               st));
+  const bool nested = !p.nested.empty();
   if (!plain) {
-    HIPCHK(launch_sample(ex->d_sample.as<SampleJob>(), (int64_t)p.sample.size(),
-                         ex->d_lib.as<int32_t>(), st));
+    if (nested)
+      HIPCHK(launch_sample_nested(ex->d_nested.as<NestedJob>(), (int64_t)p.nested.size(),
+                                  ex->d_scratch.as<int32_t>(), ex->d_lib.as<int32_t>(), st));
+    else
+      HIPCHK(launch_sample(ex->d_sample.as<SampleJob>(), (int64_t)p.sample.size(),
+                           ex->d_lib.as<int32_t>(), st));
     HIPCHK(launch_gather(ex->d_gather.as<GatherJob>(), (int64_t)p.gather.size(),
                          p.max_sorted_n_e, ex->d_emb.as<float>(), ex->d_lib.as<int32_t>(),
                          ex->d_order.as<int32_t>(), ex->d_pts.as<float>(),
@@ -161,7 +172,15 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
         ev = take_events(c);
         HIPCHK(hipEventRecord(ev.a, st));
       }
-      if (p.spec.M > 0)
+      if (nested)
+        HIPCHK(launch_crossmap_nested(E, p.mode, grid, ex->d_rz.as<Realization>(),
+                                      ex->d_items.as<Item>() + p.e_first[E], n, next,
+                                      ex->d_emb.as<float>(), ex->d_pts.as<float>(),
+                                      ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
+                                      ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
+                                      ex->d_segs.as<int32_t>(), ex->d_partial.as<Moments>(),
+                                      p.window, st));
+      else if (p.spec.M > 0)
         HIPCHK(launch_crossmap_multi(E, p.mode, grid, ex->d_rz.as<Realization>(),
                                      ex->d_self.as<int32_t>(),
                                      ex->d_items.as<Item>() + p.e_first[E], n, next,
@@ -234,6 +253,9 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                  (int64_t)p.rz.size(), p.spec.M, ex->d_partial.p,
                                  (int64_t)p.spec.L.size() * p.spec.r, ex->d_out.as<double>(),
                                  st));
+  else if (nested)
+    HIPCHK(launch_finalize(ex->d_rz_fin.as<Realization>(), (int64_t)p.rz_fin.size(),
+                           ex->d_partial.as<Moments>(), ex->d_out.as<double>(), st));
   else
     HIPCHK(launch_finalize(ex->d_rz.as<Realization>(), (int64_t)p.rz.size(),
                            ex->d_partial.as<Moments>(), ex->d_out.as<double>(), st));
@@ -271,7 +293,7 @@ void run(ccm_ctx* c, Exec* ex, hipStream_t st) {
     c->prof.pairs += p.pairs;
     c->prof.flops += p.flops;
     c->prof.predictions += p.preds;
-    c->prof.realizations += (double)p.rz.size();
+    c->prof.realizations += (double)p.n_rho;
     c->prof.table_realizations += (double)p.table_rz;
   }
 }
@@ -453,6 +475,33 @@ ccm_status ccm_library(ccm_ctx* c, int64_t N_e, int32_t E, int32_t tau, int64_t 
     out.ensure(L_eff * 4);
     HIPCHK(launch_sample(job.as<SampleJob>(), 1, out.as<int32_t>(), c->stream));
     HIPCHK(hipMemcpyAsync(idx_out, out.p, L_eff * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+ccm_status ccm_nested_library(ccm_ctx* c, int64_t N_e, int32_t E, int32_t tau,
+                              int32_t r_index, uint64_t seed, int64_t n_out,
+                              int32_t* idx_out) {
+  return guarded(c, [&] {
+    if (!idx_out) fail(CCM_E_INVAL, "idx_out is NULL");
+    if (N_e < 1 || n_out < 1 || n_out > N_e || N_e > INT32_MAX)
+      fail(CCM_E_INVAL, "need 1 <= n_out <= N_e < 2^31");
+    if (E < 1 || E > kMaxE || tau < 1) fail(CCM_E_INVAL, "E in [1, 10] and tau >= 1");
+    DevBuf job, scratch, out;
+    NestedJob nj{};
+    nj.seed = seed;
+    nj.n_e = N_e;
+    nj.n_out = n_out;
+    nj.E = E;
+    nj.tau = tau;
+    nj.r_index = r_index;
+    std::vector<NestedJob> j{nj};
+    upload(job, j);
+    scratch.ensure(N_e * 4);
+    out.ensure(n_out * 4);
+    HIPCHK(launch_sample_nested(job.as<NestedJob>(), 1, scratch.as<int32_t>(),
+                                out.as<int32_t>(), c->stream));
+    HIPCHK(hipMemcpyAsync(idx_out, out.p, n_out * 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   });
 }

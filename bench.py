@@ -16,7 +16,8 @@ traffic from the committed counter summary when it matches the kernel
 sources), the other workloads of the method (`workloads`: small coupled map
 with plain vs batched launches, long noisy series, 64-series causal matrix),
 the run-time elasticity study (`elasticity`), the same workloads through the
-paper's distance indexing table (`index_table`), the served form's p50/p99 job
+paper's distance indexing table (`index_table`), the sweep and long series
+with nested libraries (`nested`), the served form's p50/p99 job
 latency on a Poisson job stream (`served`), and the CPU oracle timed on a
 bounded random sample of the same realizations.
 """
@@ -252,6 +253,39 @@ def table_leg(ctx, torch, dev, stream, steps=3):
     return out
 
 
+def nested_leg(ctx, torch, dev, stream, steps=3):
+    """Nested libraries across L (flag CCM_FLAG_NESTED): the sweep and the
+    long series with the libraries of one r drawn as prefixes of one
+    ordering, so a query scans the largest library once and takes a
+    snapshot at every size.  Different draws from the default (rho differs),
+    tested against the oracle's nested mode."""
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = {}
+    w = synth.workload_sweep()
+    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+    rho = torch.empty((2, len(w.E), len(w.tau), len(w.L), w.r), **f64)
+    fn = lambda: ctx.ccm_sweep_dev(X, Y, w.E, w.tau, w.L, w.r, w.seed, rho, stream=stream,
+                                   flags=capi.CCM_FLAG_NESTED)
+    el, _ = _timed(ctx, torch, fn, steps, False)
+    _, p = _timed(ctx, torch, fn, 1, True)
+    out["sweep"] = {"workload": w.name, "ms_per_call": el * 1e3,
+                    "predictions_per_sec": p["predictions"] / el,
+                    "rho_realizations_per_sec": p["realizations"] / el,
+                    "pairs": p["pairs"], "kernel_ms": p["kernel_ms"],
+                    "kernel_tflops": p["flops"] / p["kernel_ms"] / 1e9}
+    w = synth.workload_long()
+    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+    a, b = torch.empty((len(w.L), w.r), **f64), torch.empty((len(w.L), w.r), **f64)
+    fn = lambda: ctx.ccm_dev(X, Y, w.E[0], w.tau[0], w.L, w.r, w.seed, a, b, stream=stream,
+                             flags=capi.CCM_FLAG_NESTED)
+    el, _ = _timed(ctx, torch, fn, 1, False)
+    _, p = _timed(ctx, torch, fn, 1, True)
+    out["long"] = {"workload": w.name, "ms_per_call": el * 1e3,
+                   "predictions_per_sec": p["predictions"] / el, "pairs": p["pairs"],
+                   "kernel_tflops": p["flops"] / p["kernel_ms"] / 1e9}
+    return out
+
+
 def elasticity_leg(ctx, torch, dev, stream, reps=3):
     """Run time as one parameter doubles, after the paper's parameter study
     (Section 4.2, Table 2): N = 4000, r = 500; each case fixes the varied
@@ -446,6 +480,7 @@ def main():
         out["workloads"] = workloads_leg(ctx, torch, dev, stream)
         out["elasticity"] = elasticity_leg(ctx, torch, dev, stream)
         out["index_table"] = table_leg(ctx, torch, dev, stream)
+        out["nested"] = nested_leg(ctx, torch, dev, stream)
     if a.serve_jobs > 0:
         print(f"bench: served leg, {a.serve_jobs} jobs", file=sys.stderr, flush=True)
         ctx.profile_enable(False)

@@ -431,7 +431,7 @@ Plan make_plan_matrix(const Spec& s) {
           R.table_off = table_for(p, R.emb_off, ne, E);
           R.table_w = (int32_t)std::min<int64_t>(kTableWidth, ne);
           p.e_table_ne[E] = std::max(p.e_table_ne[E], (int)ne);
-          p.table_rz += 1;
+          p.table_rz += M - 1;   // rho values, like n_rho
         }
         GatherJob gj{};
         gj.emb_off = R.emb_off;

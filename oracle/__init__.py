@@ -98,6 +98,9 @@ class Oracle:
         L.oracle_ccm_nested.argtypes = [P, P, i64, i32, i32, P, i32, i32, u64, i32,
                                         P, P, P]
         L.oracle_ccm_nested.restype = C.c_int
+        L.oracle_ccm_shared_e.argtypes = [P, P, i64, P, i32, i32, P, i32, i32, u64, i32,
+                                          P, P, P]
+        L.oracle_ccm_shared_e.restype = C.c_int
         self.lib = L
         self.path = path
 
@@ -204,6 +207,20 @@ class Oracle:
         self._check(self.lib.oracle_ccm_nested(_ptr(X), _ptr(Y), len(X), E, tau, _ptr(Ls),
                                                nL, r, seed & MASK64, excl, _ptr(rxy),
                                                _ptr(ryx), _ptr(le)))
+        return rxy, ryx, le
+
+    def ccm_shared_e(self, X, Y, Es, tau, L, r, seed, excl=0):
+        """E-sweep sharing for one tau: rho_xy[e][l][r], rho_yx[e][l][r], L_eff[l]."""
+        X, Y = _f64(X), _f64(Y)
+        Ea = np.ascontiguousarray(Es, dtype=np.int32)
+        Ls = np.ascontiguousarray(L, dtype=np.int64)
+        nE, nL = len(Ea), len(Ls)
+        rxy = np.empty((nE, nL, r))
+        ryx = np.empty((nE, nL, r))
+        le = np.empty(nL, dtype=np.int64)
+        self._check(self.lib.oracle_ccm_shared_e(_ptr(X), _ptr(Y), len(X), _ptr(Ea), nE, tau,
+                                                 _ptr(Ls), nL, r, seed & MASK64, excl,
+                                                 _ptr(rxy), _ptr(ryx), _ptr(le)))
         return rxy, ryx, le
 
     def status_of_ccm(self, X, Y, N, E, tau, L, r, excl=0):

@@ -54,6 +54,14 @@
  * positions needed: step k swaps position k with position
  * k + floor(z_k (N_e - k) / 2^64), z_k the k-th output of the SplitMix64
  * stream keyed by (seed, E, tau, r_index), folded as above.
+ *
+ * Option of the build: E-sweep sharing.  For a list of E with maximum
+ * E_max, every E uses the same points, the times t >= (E_max - 1) tau
+ * (N_c = N - (E_max - 1) tau of them, point c at time c + (E_max - 1) tau,
+ * coordinates S[t - k tau] for k < E), the same queries (all N_c points)
+ * and, per (tau, L, r), the same library: selection sampling over N_c
+ * points with the stream keyed by (seed, 0, tau, L_eff, r_index) (the
+ * embedding dimension replaced by 0).  Exclusion is in time steps as usual.
  */
 #include <math.h>
 #include <stdint.h>
@@ -464,6 +472,62 @@ int oracle_ccm_nested(const double *X, const double *Y, int64_t N, int32_t E,
         }
     }
     free(perm);
+    return st;
+}
+
+/*
+ * Cross-map with E-sweep sharing (see the header) for one tau:
+ * rho_xy[e][l][r] and rho_yx[e][l][r] for E = Es[e].  Point c of the common
+ * range is embedded point c of E in the series shifted by
+ * (E_max - E) tau, so each E runs the plain realization on shifted series.
+ */
+int oracle_ccm_shared_e(const double *X, const double *Y, int64_t N, const int32_t *Es,
+                        int32_t nE, int32_t tau, const int64_t *L, int32_t nL, int32_t r,
+                        uint64_t seed, int32_t excl, double *rho_xy, double *rho_yx,
+                        int64_t *L_eff)
+{
+    if (!X || !Y || !Es || !L || !rho_xy || !rho_yx || N < 2 || nE < 1 || tau < 1 ||
+        nL < 1 || r < 1)
+        return OR_EINVAL;
+    if (!valid_series(X, N) || !valid_series(Y, N))
+        return OR_EINVAL;
+    int32_t Emax = 0;
+    for (int32_t e = 0; e < nE; ++e) {
+        if (Es[e] < 1 || Es[e] > 10)
+            return OR_EINVAL;
+        if (Es[e] > Emax)
+            Emax = Es[e];
+    }
+    const int64_t Nc = N - (int64_t)(Emax - 1) * tau;
+    if (Nc < Emax + 2)
+        return OR_EINVAL;
+    for (int32_t l = 0; l < nL; ++l) {
+        const int64_t le = L[l] < Nc ? L[l] : Nc;
+        if (L[l] < Emax + 2 || le < min_library(Emax, excl))
+            return OR_EINVAL;
+        if (L_eff)
+            L_eff[l] = le;
+    }
+    int32_t *lib = (int32_t *)malloc(sizeof(int32_t) * (size_t)Nc);
+    if (!lib)
+        return OR_ENOMEM;
+    int st = OR_OK;
+    for (int32_t l = 0; l < nL && st == OR_OK; ++l) {
+        const int64_t le = L[l] < Nc ? L[l] : Nc;
+        for (int32_t q = 0; q < r && st == OR_OK; ++q) {
+            oracle_sample_library(seed, 0, tau, le, q, Nc, lib);
+            for (int32_t e = 0; e < nE && st == OR_OK; ++e) {
+                const int64_t d = (int64_t)(Emax - Es[e]) * tau;
+                const int64_t at = ((int64_t)e * nL + l) * r + q;
+                st = oracle_neighbors(Y + d, X + d, N - d, Es[e], tau, lib, le, excl, 0,
+                                      NULL, NULL, NULL, &rho_xy[at]);
+                if (st == OR_OK)
+                    st = oracle_neighbors(X + d, Y + d, N - d, Es[e], tau, lib, le, excl, 0,
+                                          NULL, NULL, NULL, &rho_yx[at]);
+            }
+        }
+    }
+    free(lib);
     return st;
 }
 

@@ -390,6 +390,57 @@ def pin_nested_ccm(orc):
     assert np.array_equal(rxy[2], ixy[0]) and np.array_equal(ryx[3], iyx[0])
 
 
+def pin_shared_e(orc):
+    """E-sweep sharing: one E alone with the full common range is the default
+    cross map at the full library; every (E, L, r) is the realization over
+    the series shifted by (E_max - E) tau with the library drawn over the
+    N_c common points by the key without E."""
+    x, y = synth.coupled_logistic(300)
+    for E in (2, 4):
+        ne = 300 - (E - 1) * 2
+        sxy, syx, _ = orc.ccm_shared_e(x, y, [E], 2, [ne], 3, 5)
+        dxy, dyx, _ = orc.ccm(x, y, E, 2, [ne], 3, 5)
+        assert np.array_equal(sxy[0], dxy) and np.array_equal(syx[0], dyx)
+    Es, tau, L, r, seed = [1, 3, 6], 2, [25, 120, 400], 2, 13
+    rxy, ryx, le = orc.ccm_shared_e(x, y, Es, tau, L, r, seed)
+    nc = 300 - (6 - 1) * tau
+    assert le.tolist() == [25, 120, nc]
+    for ie, E in enumerate(Es):
+        d = (6 - E) * tau
+        for il, l in enumerate(le):
+            for q in range(r):
+                lib = orc.sample_library(seed, 0, tau, int(l), q, nc)
+                assert rxy[ie, il, q] == orc.neighbors(y[d:], x[d:], E, tau, lib)[3]
+                assert ryx[ie, il, q] == orc.neighbors(x[d:], y[d:], E, tau, lib)[3]
+
+
+def pin_shared_e_python(orc):
+    """E = 1 inside a shared sweep, computed independently: common points at
+    times c + (E_max - 1) tau, binary32 squared differences (the product
+    diff * diff, which is the chain's first term), stable sort, exp weights,
+    numpy Pearson."""
+    x, y = synth.coupled_logistic(220)
+    Es, tau, L, r, seed = [1, 4], 3, [60], 2, 29
+    rxy, _, _ = orc.ccm_shared_e(x, y, Es, tau, L, r, seed)
+    off = (4 - 1) * tau
+    nc = 220 - off
+    yf = y.astype(np.float32)
+    for q in range(r):
+        lib = orc.sample_library(seed, 0, tau, 60, q, nc)
+        pred = np.empty(nc)
+        for c in range(nc):
+            cand = [j for j in lib if j != c]
+            diff = np.array([yf[c + off] - yf[j + off] for j in cand], dtype=np.float32)
+            d2 = diff * diff                       # binary32 product: RN(diff^2)
+            order = np.argsort(d2, kind="stable")[:2]
+            dist = np.sqrt(d2[order].astype(np.float64))
+            u = np.exp(-dist / dist[0]) if dist[0] > 0 else (dist == 0).astype(float)
+            w = u / u.sum()
+            pred[c] = float(np.sum(w * x[np.asarray(cand)[order] + off]))
+        rho = np.corrcoef(x[off:off + nc], pred)[0, 1]
+        assert abs(rxy[0, 0, q] - rho) < 1e-12, (q, rxy[0, 0, q], rho)
+
+
 def pin_input_rules(orc):
     """Invalid inputs are refused; L above N_e is clamped, not refused."""
     x = np.linspace(0.1, 0.9, 50)
@@ -426,5 +477,7 @@ ALL_PINS = [
     pin_nested_structure,
     pin_nested_uniform,
     pin_nested_ccm,
+    pin_shared_e,
+    pin_shared_e_python,
     pin_input_rules,
 ]

@@ -44,6 +44,10 @@ MUTANTS = [
     ("nested key drops r",
      "    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)r_index);\n    return s;\n}\n\n/*\n * First n_out",
      "    return s;\n}\n\n/*\n * First n_out"),
+    ("shared E without the shift", "const int64_t d = (int64_t)(Emax - Es[e]) * tau;",
+     "const int64_t d = 0;"),
+    ("shared library keyed by E", "oracle_sample_library(seed, 0, tau, le, q, Nc, lib);",
+     "oracle_sample_library(seed, Emax, tau, le, q, Nc, lib);"),
     ("nested library is a suffix", "st = oracle_neighbors(Y, X, N, E, tau, perm, le,",
      "st = oracle_neighbors(Y, X, N, E, tau, perm + (Lmax - le), le,"),
     ("splitmix constant", "0xbf58476d1ce4e5b9ULL", "0xbf58476d1ce4e5b8ULL"),

@@ -286,6 +286,27 @@ def nested_leg(ctx, torch, dev, stream, steps=3):
     return out
 
 
+def shared_e_leg(ctx, torch, dev, stream, default_ms, steps=3):
+    """E-sweep sharing (flag CCM_FLAG_SHARED_E): the sweep with every E on
+    E_max's common points and one library per (tau, L, r), so one scan per
+    (tau, L, r, direction) yields all ten E.  Different draws from the
+    default (rho differs), tested against the oracle's shared-E mode."""
+    f64 = dict(dtype=torch.float64, device=dev)
+    w = synth.workload_sweep()
+    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+    rho = torch.empty((2, len(w.E), len(w.tau), len(w.L), w.r), **f64)
+    fn = lambda: ctx.ccm_sweep_dev(X, Y, w.E, w.tau, w.L, w.r, w.seed, rho, stream=stream,
+                                   flags=capi.CCM_FLAG_SHARED_E)
+    el, _ = _timed(ctx, torch, fn, steps, False)
+    _, p = _timed(ctx, torch, fn, 1, True)
+    return {"workload": w.name, "ms_per_call": el * 1e3,
+            "predictions_per_sec": p["predictions"] / el,
+            "rho_realizations_per_sec": p["realizations"] / el,
+            "speedup_over_default_sweep": default_ms / (el * 1e3),
+            "pairs": p["pairs"], "kernel_ms": p["kernel_ms"],
+            "kernel_tflops": p["flops"] / p["kernel_ms"] / 1e9}
+
+
 def elasticity_leg(ctx, torch, dev, stream, reps=3):
     """Run time as one parameter doubles, after the paper's parameter study
     (Section 4.2, Table 2): N = 4000, r = 500; each case fixes the varied
@@ -481,6 +502,7 @@ def main():
         out["elasticity"] = elasticity_leg(ctx, torch, dev, stream)
         out["index_table"] = table_leg(ctx, torch, dev, stream)
         out["nested"] = nested_leg(ctx, torch, dev, stream)
+        out["shared_e"] = shared_e_leg(ctx, torch, dev, stream, out["ms_per_step"])
     if a.serve_jobs > 0:
         print(f"bench: served leg, {a.serve_jobs} jobs", file=sys.stderr, flush=True)
         ctx.profile_enable(False)

@@ -114,9 +114,22 @@ typedef struct {
    N_e * max(L_eff) pairs per (E, tau, r, direction) instead of
    N_e * sum(L_eff).  The rho values differ from the default draws (the
    libraries are correlated across L).  ccm and ccm_sweep (and their device
-   forms) only, with query_set 0; not with CCM_FLAG_TABLE or CCM_FLAG_PLAIN
-   (CCM_E_INVAL). */
+   forms) only, with query_set 0; not with CCM_FLAG_TABLE, CCM_FLAG_PLAIN or
+   CCM_FLAG_SHARED_E (CCM_E_INVAL). */
 #define CCM_FLAG_NESTED 16u
+/* E-sweep sharing (an option of this library, not of the paper): for each
+   tau, every E of the call uses the points that E_max (the largest E
+   listed) can embed -- N_c = N - (E_max-1) tau of them, point c at time
+   c + (E_max-1) tau, its first E lag coordinates as E's point -- and one
+   library per (tau, L, r) drawn over those N_c points by the SplitMix64
+   stream keyed by (seed, 0, tau, L_eff, r).  Each E is then the default
+   cross map of the series shifted by (E_max-E) tau, and one scan per
+   (tau, L, r, direction) computes every E's neighbours: the binary32
+   distance after E coordinates is E's d2.  The rho values differ from the
+   default draws (fewer points for E < E_max, other libraries).  ccm and
+   ccm_sweep (and their device forms) only, with query_set 0; not with
+   CCM_FLAG_TABLE, CCM_FLAG_NESTED or CCM_FLAG_PLAIN (CCM_E_INVAL). */
+#define CCM_FLAG_SHARED_E 32u
 
 /* Create a context on HIP device `device`.  *out receives the handle. */
 ccm_status ccm_create(int device, ccm_ctx **out);

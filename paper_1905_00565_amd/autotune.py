@@ -1,12 +1,13 @@
-"""Pick the cross-map kernel's launch shape for each embedding dimension E.
+"""Pick the cross-map kernels' launch shapes.
 
 The hot kernel has three shape parameters per E (see ``csrc/ccm_tune.h``):
 Q, the queries each lane holds; G, the library candidates evaluated per
 trigger check; and W, a minimum of resident wavefronts per SIMD imposed on
-the register allocator (0: none).  All are compile-time, so candidates are
-separate builds of the kernel translation unit.  Each build ("column") gives every E one
-candidate from that E's list; every column is timed on the same sweep and
-each E keeps its fastest candidate.
+the register allocator (0: none).  The E-sweep-sharing scan has the same
+three per E_max (``--kind shared``).  All are compile-time, so candidates
+are separate builds of the kernel translation unit.  Each build ("column")
+gives every E one candidate from that E's list; every column is timed on
+the same sweep and each E keeps its fastest candidate.
 
 Two phases, so that compilation stays off the GPU host:
 
@@ -14,16 +15,18 @@ Two phases, so that compilation stays off the GPU host:
     python -m paper_1905_00565_amd.autotune time --out T.h  # GPU: time, write table
 
 ``time`` runs one child process per column (a process loads one libccm) and
-writes the chosen table as a header in the format of ``csrc/ccm_tune.h``,
-plus a JSON report next to it.  Results do not depend on the shape (the
-neighbour selection is exact whatever the visiting order and grouping), so
-the choice is about speed alone.
+writes the chosen tables as a header in the format of ``csrc/ccm_tune.h``
+(the tables of the other kind are kept as they are), plus a JSON report
+next to it.  Results do not depend on the shape (the neighbour selection is
+exact whatever the visiting order and grouping), so the choice is about
+speed alone.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -47,13 +50,31 @@ CANDIDATES = {
 }
 
 
-def columns():
+# E-sweep sharing, per E_max: (Q, G) or (Q, G, W); the first is the current choice.
+SHARED_CANDIDATES = {
+    1: [(2, 8), (4, 8), (2, 16), (1, 16), (3, 8)],
+    2: [(2, 8), (4, 8), (2, 12), (3, 8), (2, 4)],
+    3: [(2, 8), (3, 8), (2, 6), (2, 4), (1, 8)],
+    4: [(1, 8), (2, 4), (2, 6), (2, 8), (3, 4)],
+    5: [(1, 6), (2, 6), (2, 4), (1, 8), (2, 3)],
+    6: [(1, 6), (1, 6, 4), (1, 4, 4), (2, 4), (1, 3)],
+    7: [(1, 4), (1, 4, 3), (1, 3, 4), (1, 6), (1, 2)],
+    8: [(1, 4), (1, 4, 3), (1, 3, 3), (1, 2), (1, 6)],
+    9: [(1, 4), (1, 4, 3), (1, 3, 3), (1, 2), (1, 6)],
+    10: [(1, 4, 3), (1, 4), (1, 3, 3), (1, 2), (1, 6)],
+}
+MACROS = {"default": ("CCM_TUNE_Q", "CCM_TUNE_G", "CCM_TUNE_W"),
+          "shared": ("CCM_SHARED_Q", "CCM_SHARED_G", "CCM_SHARED_W")}
+
+
+def columns(kind="default"):
     """Column k gives every E its k-th candidate (or its last, if it has fewer);
     a candidate is (Q, G) or (Q, G, W)."""
-    n = max(len(v) for v in CANDIDATES.values())
+    cand = CANDIDATES if kind == "default" else SHARED_CANDIDATES
+    n = max(len(v) for v in cand.values())
     cols = []
     for k in range(n):
-        pick = [CANDIDATES[e][min(k, len(CANDIDATES[e]) - 1)] for e in range(1, 11)]
+        pick = [cand[e][min(k, len(cand[e]) - 1)] for e in range(1, 11)]
         q = [0] + [c[0] for c in pick]
         g = [0] + [c[1] for c in pick]
         w = [0] + [c[2] if len(c) > 2 else 0 for c in pick]
@@ -65,10 +86,11 @@ def _brace(v):
     return "{" + ", ".join(str(x) for x in v) + "}"
 
 
-def _build_column(k, q, g, w):
+def _build_column(k, q, g, w, kind="default"):
     obj = os.path.join(TUNE_DIR, f"kernels_{k}.o")
-    cmd = [B.hipcc(), *B.common_flags(), f"-DCCM_TUNE_Q={_brace(q)}", f"-DCCM_TUNE_G={_brace(g)}",
-           f"-DCCM_TUNE_W={_brace(w)}",
+    mq, mg, mw = MACROS[kind]
+    cmd = [B.hipcc(), *B.common_flags(), f"-D{mq}={_brace(q)}", f"-D{mg}={_brace(g)}",
+           f"-D{mw}={_brace(w)}",
            "-c", os.path.join(B.CSRC, "ccm_kernels.hip"), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -86,19 +108,22 @@ def _build_column(k, q, g, w):
     return lib
 
 
-def build_columns(jobs: int = 8):
+def build_columns(jobs: int = 8, kind: str = "default"):
     B.build_library()                       # the other objects, and a current library
     os.makedirs(TUNE_DIR, exist_ok=True)
-    cols = columns()
+    cols = columns(kind)
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        libs = list(ex.map(lambda a: _build_column(*a), [(k, *c) for k, c in enumerate(cols)]))
+        libs = list(ex.map(lambda a: _build_column(*a, kind),
+                           [(k, *c) for k, c in enumerate(cols)]))
     with open(os.path.join(TUNE_DIR, "columns.json"), "w") as f:
-        json.dump({"columns": cols, "libs": [os.path.basename(x) for x in libs]}, f)
+        json.dump({"kind": kind, "columns": cols,
+                   "libs": [os.path.basename(x) for x in libs]}, f)
     return libs
 
 
-def time_column(r: int, n: int):
-    """Child process: time every E of the sweep with the library in CCM_LIBRARY."""
+def time_column(r: int, n: int, kind: str = "default"):
+    """Child process: time every E of the sweep (or, for the shared scan, the
+    sweep of E = 1..E_max for every E_max) with the library in CCM_LIBRARY."""
     import torch
     from . import capi, synth
     w = synth.workload_sweep(n=n, r=r)
@@ -108,13 +133,15 @@ def time_column(r: int, n: int):
     ctx = capi.Context(0)
     ctx.profile_enable(True)
     out = {}
+    flags = capi.CCM_FLAG_SHARED_E if kind == "shared" else 0
     for e in w.E:
-        rho = torch.empty((2, 1, len(w.tau), len(w.L), r), dtype=torch.float64, device=dev)
+        es = list(range(1, e + 1)) if kind == "shared" else [e]
+        rho = torch.empty((2, len(es), len(w.tau), len(w.L), r), dtype=torch.float64, device=dev)
         st = torch.cuda.current_stream()
-        ctx.ccm_sweep_dev(X, Y, [e], w.tau, w.L, r, w.seed, rho, stream=st)
+        ctx.ccm_sweep_dev(X, Y, es, w.tau, w.L, r, w.seed, rho, stream=st, flags=flags)
         torch.cuda.synchronize()
         ctx.profile_read(reset=True)
-        ctx.ccm_sweep_dev(X, Y, [e], w.tau, w.L, r, w.seed, rho, stream=st)
+        ctx.ccm_sweep_dev(X, Y, es, w.tau, w.L, r, w.seed, rho, stream=st, flags=flags)
         torch.cuda.synchronize()
         p = ctx.profile_read(reset=True)
         out[e] = {"ms": p["kernel_ms"], "flops": p["flops"], "rho_sum": float(rho.sum().item())}
@@ -123,7 +150,20 @@ def time_column(r: int, n: int):
     print(json.dumps(out), flush=True)
 
 
-def write_header(path, q, g, w, note):
+def read_tables(path):
+    """The six tables of an existing ccm_tune.h (macro name -> list)."""
+    with open(path) as f:
+        text = f.read()
+    tables = {}
+    for name in MACROS["default"] + MACROS["shared"]:
+        m = re.search(r"#define " + name + r" \{([^}]*)\}", text)
+        tables[name] = [int(x) for x in m.group(1).split(",")]
+    return tables
+
+
+def write_header(path, tables, note):
+    q, g, w = (tables[m] for m in MACROS["default"])
+    sq, sg, sw = (tables[m] for m in MACROS["shared"])
     text = f"""// ccm_tune.h -- launch shape of the cross-map kernel for each embedding
 // dimension E (index 0 unused).  Written by paper_1905_00565_amd/autotune.py
 // from timings of the E = 1..10, tau = 1..5 sweep on coupled-logistic series
@@ -148,10 +188,27 @@ def write_header(path, q, g, w, note):
 #define CCM_TUNE_G {_brace(g)}
 #endif
 
+// E-sweep sharing: the scan at E_max keeps E_max (E_max + 3) / 2 keys per
+// query, so its shape is chosen per E_max (index E_max):
+//   kSharedQ  queries per lane;  kSharedG  candidates per trigger check;
+//   kSharedW  minimum wavefronts per SIMD (0: free)
+#ifndef CCM_SHARED_Q
+#define CCM_SHARED_Q {_brace(sq)}
+#endif
+#ifndef CCM_SHARED_G
+#define CCM_SHARED_G {_brace(sg)}
+#endif
+#ifndef CCM_SHARED_W
+#define CCM_SHARED_W {_brace(sw)}
+#endif
+
 namespace ccmk {{
 constexpr int kTuneQ[11] = CCM_TUNE_Q;
 constexpr int kTuneG[11] = CCM_TUNE_G;
 constexpr int kTuneW[11] = CCM_TUNE_W;
+constexpr int kSharedQ[11] = CCM_SHARED_Q;
+constexpr int kSharedG[11] = CCM_SHARED_G;
+constexpr int kSharedW[11] = CCM_SHARED_W;
 }}  // namespace ccmk
 """
     with open(path, "w") as f:
@@ -162,12 +219,13 @@ def time_columns(out: str, r: int, n: int, timeout: int):
     with open(os.path.join(TUNE_DIR, "columns.json")) as f:
         meta = json.load(f)
     cols, libs = meta["columns"], meta["libs"]
+    kind = meta.get("kind", "default")
     results = []
     for k, lib in enumerate(libs):
         print(f"column {k}: Q={cols[k][0][1:]} G={cols[k][1][1:]} W={cols[k][2][1:]}", flush=True)
         env = dict(os.environ, CCM_LIBRARY=os.path.join(TUNE_DIR, lib))
         res = subprocess.run([sys.executable, "-u", "-m", "paper_1905_00565_amd.autotune",
-                              "_child", "--r", str(r), "--n", str(n)],
+                              "_child", "--r", str(r), "--n", str(n), "--kind", kind],
                              env=env, capture_output=True, text=True, timeout=timeout,
                              cwd=B.ROOT)
         if res.returncode != 0:
@@ -189,7 +247,11 @@ def time_columns(out: str, r: int, n: int, timeout: int):
         report[e] = {"choice": [q[-1], g[-1], wv[-1]], "ms": ms,
                      "candidates": [[cols[k][i][e] for i in range(3)] for k in range(len(cols))],
                      "tflops": results[best][e]["flops"] / ms[best] / 1e9}
-    write_header(out, q, g, wv, f"N = {n}, r = {r} per (E, tau, L)")
+    current = os.path.join(B.CSRC, "ccm_tune.h")
+    tables = read_tables(out if os.path.exists(out) else current)
+    for name, vals in zip(MACROS[kind], (q, g, wv)):
+        tables[name] = vals
+    write_header(out, tables, f"N = {n}, r = {r} per (E, tau, L)")
     with open(os.path.splitext(out)[0] + ".json", "w") as f:
         json.dump(report, f, indent=1)
     for e in range(1, 11):
@@ -205,14 +267,15 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("--timeout", type=int, default=240)
+    ap.add_argument("--kind", choices=["default", "shared"], default="default")
     a = ap.parse_args(argv)
     if a.phase == "build":
-        for lib in build_columns(a.jobs):
+        for lib in build_columns(a.jobs, a.kind):
             print("built", lib)
     elif a.phase == "time":
         time_columns(a.out, a.r, a.n, a.timeout)
     else:
-        time_column(a.r, a.n)
+        time_column(a.r, a.n, a.kind)
 
 
 if __name__ == "__main__":

@@ -32,6 +32,7 @@ CCM_FLAG_NO_GRAPH = 2
 CCM_FLAG_PERSISTENT = 4
 CCM_FLAG_TABLE = 8
 CCM_FLAG_NESTED = 16
+CCM_FLAG_SHARED_E = 32
 CCM_TABLE_WIDTH = 1024
 
 # Every symbol include/ccm.h declares (checked by the ABI test).

@@ -154,6 +154,9 @@ struct Plan {
   std::vector<int32_t> segs;          // segment bounds of every chain
   std::vector<Realization> rz_fin;
   int64_t n_rho = 0;                  // rho values produced
+  // E-sweep sharing (CCM_FLAG_SHARED_E): rz holds one scan per (tau, L, r,
+  // direction) at E_max, rz_fin one record per rho
+  int32_t shared_emax = 0;
 };
 
 // Whether a realization walks a distance indexing table, and the offset of
@@ -161,9 +164,22 @@ struct Plan {
 bool use_table(const Plan& p, int E, int64_t ne, int64_t le);
 int64_t table_for(Plan& p, int64_t emb_off, int64_t ne, int E);
 
-// Order set of (series, tau) -- tau 0 for the value order -- created on
-// first use; returns its offset in the order pool.
-int64_t order_set(Plan& p, int series, int32_t tau);
+// The key of an order set: dims and lags as in OrderJob.
+struct OrderKey {
+  int32_t dims;
+  int32_t lag[4];
+};
+// Visiting order of the embedding of dimension E with delay tau: the value
+// order for E = 1, a Hilbert curve over the two oldest lag coordinates else.
+OrderKey embedding_order(int32_t E, int32_t tau);
+// E-sweep sharing: visiting order of E_max's common points, keyed on the
+// newest lag coordinates (the ones every E of the sweep uses): the two
+// newest, or for E_max >= 8 (where the long lists of the large E dominate)
+// a 4-dimensional curve over the four newest.
+OrderKey shared_order(int32_t Emax, int32_t tau);
+// Order set of (series, key), created on first use; returns its offset in
+// the order pool.
+int64_t order_set(Plan& p, int series, const OrderKey& key);
 
 // Validate a sweep (pair of series, E x tau grid) and lay out every
 // realization of it.

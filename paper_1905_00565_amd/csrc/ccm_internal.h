@@ -25,18 +25,23 @@ struct IngestJob {
 };
 
 // One visiting order of a series' embedded points (an "order set"): indices
-// i sorted by a key.  An embedded point i of any E has its oldest lag
-// coordinate at time i, so one set serves every E with the same delay; each
-// embedding keeps the indices below its own n_e.  tau == 0: the value S[i]
-// (used for E = 1); tau > 0: the position on a Hilbert curve over the two
-// oldest lag coordinates (S[i], S[i + tau]), each scaled to 16 bits by the
-// series' range (used for E >= 2 with that delay; i >= n - tau sorts last
-// and is never an embedded point).
+// i sorted by a key computed from a few values of the series at fixed time
+// offsets ("lags") from i -- the time of embedded point i's oldest lag
+// coordinate, so one set serves every embedding whose coordinates include
+// those times; each embedding keeps the indices below its own n_e.
+//   dims == 1: the value S[i + lag[0]];
+//   dims == 2: the position on a Hilbert curve over (S[i + lag[0]],
+//              S[i + lag[1]]), each scaled to 16 bits by the series' range;
+//   dims == 3, 4: the position on the dims-dimensional Hilbert curve over
+//              S[i + lag[d]], each scaled to 32 / dims bits.
+// An index whose lags run past the series sorts last (it is never an
+// embedded point of an embedding that uses the set).
 struct OrderJob {
   int64_t src_off;   // floats into the FP32 series pool
   int64_t key_off;   // uint32 keys (and the sorted order) of this set
   int64_t n;         // series length
-  int32_t tau;
+  int32_t dims;
+  int32_t lag[4];
   int32_t pad;
 };
 
@@ -156,6 +161,9 @@ struct Dump {
 
 // Launchers (defined with the kernels).
 int crossmap_queries_per_lane(int E, bool dump);
+// E-sweep sharing: queries per lane of the scan at E_max (its key registers
+// grow as E_max^2, so this falls with E_max).
+int shared_queries_per_lane(int emax);
 hipError_t launch_ingest(const IngestJob* jobs, int n_jobs, int64_t max_n,
                          const double* src, float* dst, hipStream_t st);
 hipError_t launch_embed(const EmbedJob* jobs, int n_jobs, int64_t max_n,
@@ -199,6 +207,14 @@ hipError_t launch_crossmap_nested(int E, int mode, int grid, const Realization* 
                                   const int32_t* qord, const int32_t* start, const double* tgt,
                                   const int32_t* seg, Moments* partial, int window,
                                   hipStream_t st);
+// E-sweep sharing: chains over E_max's embedding, one list per E <= emax;
+// partial slot of E, tile t: slot_base + (E-1) * n_tiles + t; tiles of
+// kBlock * shared_queries_per_lane(emax) queries, scan starts kWaves per tile.
+hipError_t launch_crossmap_shared(int emax, int mode, int grid, const Realization* rzs,
+                                  const Item* items, int n_items, int* next,
+                                  const float* emb, const float* pts, const int32_t* pj,
+                                  const int32_t* qord, const int32_t* start, const double* tgt,
+                                  Moments* partial, int window, hipStream_t st);
 hipError_t launch_finalize(const Realization* rzs, int64_t n_rz,
                            const Moments* partial, double* out, hipStream_t st);
 

@@ -11,7 +11,7 @@
 //   k_ingest       double series -> float series (round to nearest even)
 //   k_embed        lagged-coordinate embedding, AoS float[n_e][E]
 //   k_order_keys   visiting-order keys of each order set (value, or Hilbert
-//                  position over the two oldest lag coordinates)
+//                  position over a few lag coordinates)
 //   (sort_series)  each order set's embedded indices sorted by key
 //   k_query_order  each embedding's points in its set's visiting order
 //   k_sample       library subsamples: selection sampling driven by SplitMix64
@@ -103,8 +103,38 @@ __device__ __forceinline__ uint32_t ordered_bits(float v) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// Index on the n-dimensional Hilbert curve of b bits per axis (n <= 4,
+// n * b <= 32): Skilling's transpose form (J. Skilling, "Programming the
+// Hilbert curve", AIP Conf. Proc. 707, 2004) -- undo the excess work of the
+// recursive reflections and exchanges from the top bit down, Gray-encode
+// across axes, then read the index bits axis-interleaved, top bit first.
+__device__ __forceinline__ uint32_t hilbert_nd(uint32_t (&x)[4], int n, int b) {
+  const uint32_t top = 1u << (b - 1);
+  for (uint32_t q = top; q > 1; q >>= 1) {
+    const uint32_t low = q - 1;
+    for (int i = 0; i < n; ++i) {
+      if (x[i] & q) {
+        x[0] ^= low;
+      } else {
+        const uint32_t t = (x[0] ^ x[i]) & low;
+        x[0] ^= t;
+        x[i] ^= t;
+      }
+    }
+  }
+  for (int i = 1; i < n; ++i) x[i] ^= x[i - 1];
+  uint32_t t = 0;
+  for (uint32_t q = top; q > 1; q >>= 1)
+    if (x[n - 1] & q) t ^= q - 1;
+  for (int i = 0; i < n; ++i) x[i] ^= t;
+  uint32_t h = 0;
+  for (int bit = b - 1; bit >= 0; --bit)
+    for (int i = 0; i < n; ++i) h = (h << 1) | ((x[i] >> bit) & 1u);
+  return h;
+}
+
 // Keys of one order set (see OrderJob).  One workgroup per set: the series'
-// range first (for the 16-bit scaling), then one key per time point.
+// range first (for the scaling), then one key per time point.
 __global__ __launch_bounds__(256) void k_order_keys(const OrderJob* __restrict__ jobs,
                                                     const float* __restrict__ s32,
                                                     uint32_t* __restrict__ keys) {
@@ -113,8 +143,12 @@ __global__ __launch_bounds__(256) void k_order_keys(const OrderJob* __restrict__
   const float* __restrict__ s = s32 + J.src_off;
   uint32_t* __restrict__ k = keys + J.key_off;
   const int tid = threadIdx.x;
-  if (J.tau == 0) {
-    for (int64_t t = tid; t < J.n; t += 256) k[t] = ordered_bits(s[t]);
+  const int dims = J.dims;
+  int64_t lag_max = 0;
+  for (int d = 0; d < dims; ++d) lag_max = max(lag_max, (int64_t)J.lag[d]);
+  if (dims == 1) {
+    for (int64_t t = tid; t < J.n; t += 256)
+      k[t] = t + lag_max < J.n ? ordered_bits(s[t + J.lag[0]]) : 0xffffffffu;
     return;
   }
   float lo = __builtin_inff(), hi = -__builtin_inff();
@@ -133,16 +167,19 @@ __global__ __launch_bounds__(256) void k_order_keys(const OrderJob* __restrict__
     __syncthreads();
   }
   lo = s_lo[0];
+  const int bits = dims == 2 ? 16 : 32 / dims;
+  const float top = (float)((1u << bits) - 1u);
   const float span = s_hi[0] - lo;
-  const float scale = span > 0.f ? 65535.f / span : 0.f;
+  const float scale = span > 0.f ? top / span : 0.f;
   for (int64_t i = tid; i < J.n; i += 256) {
-    if (i >= J.n - J.tau) {
+    if (i + lag_max >= J.n) {
       k[i] = 0xffffffffu;
       continue;
     }
-    const uint32_t x = (uint32_t)fminf(65535.f, fmaxf(0.f, (s[i] - lo) * scale));
-    const uint32_t y = (uint32_t)fminf(65535.f, fmaxf(0.f, (s[i + J.tau] - lo) * scale));
-    k[i] = hilbert16(x, y);
+    uint32_t x[4] = {0u, 0u, 0u, 0u};
+    for (int d = 0; d < dims; ++d)
+      x[d] = (uint32_t)fminf(top, fmaxf(0.f, (s[i + J.lag[d]] - lo) * scale));
+    k[i] = dims == 2 ? hilbert16(x[0], x[1]) : hilbert_nd(x, dims, bits);
   }
 }
 
@@ -1187,6 +1224,228 @@ __device__ __forceinline__ void nested_item(
   }
 }
 
+// ---------------------------------------------------------------------------
+// E-sweep sharing: one scan serves every E <= EMAX
+// ---------------------------------------------------------------------------
+//
+// With the option, every E of a sweep uses the points of E_max's embedding
+// (their first E coordinates) and the same libraries.  The binary32 chain of
+// a pair after k coordinates is exactly that pair's d2 for E = k (the chain
+// runs in the same order from +0), so one pass over the library serves all
+// of them; each E keeps its own running list of E+1 keys (lists packed in
+// one array: E's list at offset (E-1)(E+2)/2).
+//
+// Fast path per group of G candidates: the chains, and per (query, E) the
+// smallest partial sum of the group; one compare per (query, E) against the
+// running E+1-th key decides whether E's list can change.  Only then are the
+// group's chains recomputed to E coordinates (the same sequence of binary32
+// operations, so the same values) and the candidates inserted, with the
+// exclusions checked exactly.
+
+template <int EMAX>
+struct SharedLists {
+  static constexpr int kTotal = EMAX * (EMAX + 3) / 2;
+  static constexpr int off(int e) { return (e - 1) * (e + 2) / 2; }
+};
+
+template <int EMAX, int Q>
+struct SharedState {
+  float qc[Q][EMAX];
+  int qi[Q];
+  double key[Q][SharedLists<EMAX>::kTotal];
+};
+
+template <int KS, int OFF, int TOT>
+__device__ __forceinline__ void insert_at(double (&key)[TOT], double c) {
+#pragma unroll
+  for (int m = KS - 1; m >= 1; --m) key[OFF + m] = kmin(kmax(key[OFF + m - 1], c), key[OFF + m]);
+  key[OFF] = kmin(key[OFF], c);
+}
+
+// d2 of candidate g to E coordinates.
+template <int EMAX, int G, int E>
+__device__ __forceinline__ float shared_d2(const Chunk<EMAX, G>& ch, int g,
+                                           const float (&q)[EMAX]) {
+  float d = q[0] - ch.p[g][0];
+  float acc = d * d;
+#pragma unroll
+  for (int k = 1; k < E; ++k) {
+    d = q[k] - ch.p[g][k];
+    acc = __builtin_fmaf(d, d, acc);
+  }
+  return acc;
+}
+
+// Slow path of list E: recompute the group's chains to E coordinates and
+// insert what enters E's list (exclusions checked exactly).
+template <int EMAX, int Q, int MODE, int G, int E>
+__device__ __forceinline__ void shared_lists(const Chunk<EMAX, G>& ch, const float (&mn)[Q][EMAX],
+                                             int window, SharedState<EMAX, Q>& S) {
+  constexpr int TOT = SharedLists<EMAX>::kTotal;
+  constexpr int OFF = SharedLists<EMAX>::off(E);
+  constexpr int KS = E + 1;
+  bool hit = false;
+#pragma unroll
+  for (int m = 0; m < Q; ++m) hit |= mn[m][E - 1] <= key_d2(S.key[m][OFF + KS - 1]);
+  if (__builtin_amdgcn_ballot_w64(hit)) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int m = 0; m < Q; ++m) {
+        const float d2 = shared_d2<EMAX, G, E>(ch, g, S.qc[m]);
+        bool ok = d2 <= key_d2(S.key[m][OFF + KS - 1]);
+        if (MODE == kExclSelf) ok = ok && ch.j[g] != S.qi[m];
+        if (MODE == kWindow) {
+          const int dj = ch.j[g] - S.qi[m];
+          ok = ok && (dj > window || dj < -window);
+        }
+        if (ok) insert_at<KS, OFF, TOT>(S.key[m], make_key(d2, ch.j[g]));
+      }
+  }
+  if constexpr (E < EMAX) shared_lists<EMAX, Q, MODE, G, E + 1>(ch, mn, window, S);
+}
+
+// Fast path: every chain of the group and, per (query, E), its smallest
+// partial sum, then one check per list.
+template <int EMAX, int Q, int MODE, int G>
+__device__ __forceinline__ void shared_chunk(const Chunk<EMAX, G>& ch, int window,
+                                             SharedState<EMAX, Q>& S) {
+  float mn[Q][EMAX];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      float d = S.qc[m][0] - ch.p[g][0];
+      float acc = d * d;
+      if (MODE == kWindow) {
+        // an excluded pair never raises a trigger (checked exactly on insert)
+        const int dj = ch.j[g] - S.qi[m];
+        if (dj <= window && dj >= -window) acc = __builtin_inff();
+      }
+      mn[m][0] = g == 0 ? acc : fminf(mn[m][0], acc);
+#pragma unroll
+      for (int k = 1; k < EMAX; ++k) {
+        d = S.qc[m][k] - ch.p[g][k];
+        acc = __builtin_fmaf(d, d, acc);
+        mn[m][k] = g == 0 ? acc : fminf(mn[m][k], acc);
+      }
+    }
+  shared_lists<EMAX, Q, MODE, G, 1>(ch, mn, window, S);
+}
+
+template <int EMAX, int Q, int MODE, int G>
+__device__ __forceinline__ void shared_group(const float* __restrict__ pts,
+                                             const int32_t* __restrict__ pj, int c, int window,
+                                             SharedState<EMAX, Q>& S) {
+  Chunk<EMAX, G> ch;
+  load_chunk<EMAX, G>(ch, pts, pj, c);
+  shared_chunk<EMAX, Q, MODE, G>(ch, window, S);
+}
+
+// Prediction of list E for each of the lane's queries, the tile's moments
+// merged over the workgroup and stored in E's slots; then the next E.
+template <int EMAX, int Q, int E>
+__device__ __forceinline__ void shared_snapshot(const Realization& R, int tile,
+                                                const double* __restrict__ tgt, int64_t off,
+                                                const SharedState<EMAX, Q>& S,
+                                                Moments* __restrict__ partial, Moments* red) {
+  constexpr int K = E + 1;
+  constexpr int OFF = SharedLists<EMAX>::off(E);
+  const int tid = threadIdx.x;
+  Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    if (S.qi[m] < 0) continue;
+    float nd[K];
+    double w[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) nd[t] = key_d2(S.key[m][OFF + t]);
+    simplex_weights<K>(nd, w);
+    double pred = 0.0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) pred += w[t] * tgt[key_j(S.key[m][OFF + t]) + off];
+    mom_add(mo, tgt[S.qi[m] + off], pred);
+  }
+  red[tid] = mo;
+  __syncthreads();
+#pragma unroll
+  for (int s2 = kBlock / 2; s2 > 0; s2 >>= 1) {
+    if (tid < s2) red[tid] = mom_merge(red[tid], red[tid + s2]);
+    __syncthreads();
+  }
+  if (tid == 0) partial[R.slot_base + (int64_t)(E - 1) * R.n_tiles + tile] = red[0];
+  __syncthreads();
+  if constexpr (E < EMAX) shared_snapshot<EMAX, Q, E + 1>(R, tile, tgt, off, S, partial, red);
+}
+
+template <int EMAX, int MODE>
+__device__ __forceinline__ void shared_item(
+    const Realization& R, int tile, const float* __restrict__ emb_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
+    const double* __restrict__ tgt_pool, Moments* __restrict__ partial, int window,
+    Moments* red) {
+  constexpr int TOT = SharedLists<EMAX>::kTotal;
+  constexpr int Q = kSharedQ[EMAX];
+  constexpr int G = kSharedG[EMAX];
+  constexpr int QT = kBlock * Q;
+  constexpr int QW = 64 * Q;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const float* __restrict__ emb = emb_pool + R.emb_off;
+  const float* __restrict__ pts = pts_pool + R.pts_off;
+  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
+  const int32_t* __restrict__ qord = qord_pool + R.qord_off;
+  const double* __restrict__ tgt = tgt_pool + R.tgt_off;
+  const int64_t off = (int64_t)(EMAX - 1) * R.tau;   // time of common point 0
+  const int L = R.l_eff;
+
+  SharedState<EMAX, Q> S;
+  bool any = false;
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    const int qq = tile * QT + wave * QW + m * 64 + lane;
+    const bool valid = qq < R.n_query;
+    any |= valid;
+    const int i = valid ? qord[qq] : 0;
+    S.qi[m] = valid ? i : -1;
+#pragma unroll
+    for (int k = 0; k < EMAX; ++k) S.qc[m][k] = emb[(int64_t)i * EMAX + k];
+#pragma unroll
+    for (int s = 0; s < TOT; ++s) S.key[m][s] = empty_key();
+  }
+
+  if (__builtin_amdgcn_ballot_w64(any)) {
+    int s0 = start_pool[(R.slot_base + tile) * kWaves + wave];
+    s0 = min(max(s0, 0), L);
+    int f = s0, b = s0;
+    const int both = min((L - s0) / G, s0 / G);
+    if (both > 0) {
+      Chunk<EMAX, G> A, B;
+      load_chunk<EMAX, G>(A, pts, pj, f);
+      for (int k = 0; k < both; ++k) {
+        settle_chunk<EMAX, G>(A);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk<EMAX, G>(B, pts, pj, b - G);
+        __builtin_amdgcn_sched_barrier(0);
+        shared_chunk<EMAX, Q, MODE, G>(A, window, S);
+        f += G;
+        settle_chunk<EMAX, G>(B);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk<EMAX, G>(A, pts, pj, k + 1 < both ? f : f - G);
+        __builtin_amdgcn_sched_barrier(0);
+        shared_chunk<EMAX, Q, MODE, G>(B, window, S);
+        b -= G;
+      }
+    }
+    for (; f + G <= L; f += G) shared_group<EMAX, Q, MODE, G>(pts, pj, f, window, S);
+    for (; b - G >= 0; b -= G) shared_group<EMAX, Q, MODE, G>(pts, pj, b - G, window, S);
+    for (; f < L; ++f) shared_group<EMAX, Q, MODE, 1>(pts, pj, f, window, S);
+    for (; b > 0; --b) shared_group<EMAX, Q, MODE, 1>(pts, pj, b - 1, window, S);
+  }
+  shared_snapshot<EMAX, Q, 1>(R, tile, tgt, off, S, partial, red);
+}
+
 // Work items are taken in list order (the host lists them longest first).
 // With next == nullptr each workgroup takes items blockIdx.x, +gridDim.x, ...;
 // otherwise workgroups pull the next item from an atomic counter that starts
@@ -1289,6 +1548,34 @@ __attribute__((amdgpu_waves_per_eu(kTuneW[E] > 0 ? kTuneW[E] : 1, 8))) void k_cr
     const Realization R = rzs[I.rz];
     nested_item<E, Q, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
                             tgt_pool, seg_pool, partial, window, red);
+    if (next == nullptr) {
+      it += gridDim.x;
+    } else {
+      if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(next, 1);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(s_next);
+      __syncthreads();
+    }
+  }
+}
+
+template <int EMAX, int MODE>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(kSharedW[EMAX] > 0 ? kSharedW[EMAX] : 1, 8)))
+void k_crossmap_shared(
+    const Realization* __restrict__ rzs, const Item* __restrict__ items,
+    int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
+    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
+    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
+    const double* __restrict__ tgt_pool, Moments* __restrict__ partial, int window) {
+  __shared__ Moments red[kBlock];
+  __shared__ int s_next;
+  int it = xcd_item(blockIdx.x, gridDim.x);
+  while (it < n_items) {
+    const Item I = items[it];
+    const Realization R = rzs[I.rz];
+    shared_item<EMAX, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
+                            tgt_pool, partial, window, red);
     if (next == nullptr) {
       it += gridDim.x;
     } else {
@@ -1421,6 +1708,10 @@ static inline unsigned blocks_for(int64_t n, int per) {
   if (b < 1) b = 1;
   if (b > 65535) b = 65535;
   return (unsigned)b;
+}
+
+int shared_queries_per_lane(int emax) {
+  return emax >= 1 && emax <= kMaxE ? kSharedQ[emax] : 0;
 }
 
 int crossmap_queries_per_lane(int E, bool dump) {
@@ -1562,6 +1853,48 @@ hipError_t launch_crossmap_nested(int E, int mode, int grid, const Realization* 
     CCM_NCASE(1) CCM_NCASE(2) CCM_NCASE(3) CCM_NCASE(4) CCM_NCASE(5)
     CCM_NCASE(6) CCM_NCASE(7) CCM_NCASE(8) CCM_NCASE(9) CCM_NCASE(10)
 #undef CCM_NCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int EMAX>
+static hipError_t launch_shared_e(int mode, int grid, const Realization* rzs,
+                                  const Item* items, int n_items, int* next,
+                                  const float* emb, const float* pts, const int32_t* pj,
+                                  const int32_t* qord, const int32_t* start, const double* tgt,
+                                  Moments* partial, int window, hipStream_t st) {
+  switch (mode) {
+    case kExclSelf:
+      k_crossmap_shared<EMAX, kExclSelf><<<grid, kBlock, 0, st>>>(
+          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial, window);
+      break;
+    case kKeepSelf:
+      k_crossmap_shared<EMAX, kKeepSelf><<<grid, kBlock, 0, st>>>(
+          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial, window);
+      break;
+    default:
+      k_crossmap_shared<EMAX, kWindow><<<grid, kBlock, 0, st>>>(
+          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial, window);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_crossmap_shared(int emax, int mode, int grid, const Realization* rzs,
+                                  const Item* items, int n_items, int* next,
+                                  const float* emb, const float* pts, const int32_t* pj,
+                                  const int32_t* qord, const int32_t* start, const double* tgt,
+                                  Moments* partial, int window, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  switch (emax) {
+#define CCM_SCASE(e)                                                                     \
+  case e:                                                                                \
+    return launch_shared_e<e>(mode, grid, rzs, items, n_items, next, emb, pts, pj, qord,  \
+                              start, tgt, partial, window, st);
+    CCM_SCASE(1) CCM_SCASE(2) CCM_SCASE(3) CCM_SCASE(4) CCM_SCASE(5)
+    CCM_SCASE(6) CCM_SCASE(7) CCM_SCASE(8) CCM_SCASE(9) CCM_SCASE(10)
+#undef CCM_SCASE
     default:
       return hipErrorInvalidValue;
   }

@@ -4,12 +4,33 @@
 
 namespace ccmh {
 
-int64_t order_set(Plan& p, int series, int32_t tau) {
+OrderKey embedding_order(int32_t E, int32_t tau) {
+  if (E == 1) return {1, {0, 0, 0, 0}};
+  return {2, {0, tau, 0, 0}};
+}
+
+OrderKey shared_order(int32_t Emax, int32_t tau) {
+  if (Emax == 1) return {1, {0, 0, 0, 0}};
+  if (Emax < 6) return {2, {(Emax - 2) * tau, (Emax - 1) * tau, 0, 0}};
+  return {4, {(Emax - 1) * tau, (Emax - 2) * tau, (Emax - 3) * tau, (Emax - 4) * tau}};
+}
+
+int64_t order_set(Plan& p, int series, const OrderKey& key) {
   const int64_t N = p.spec.N;
-  for (size_t k = 0; k < p.orders.size(); ++k)
-    if (p.orders[k].src_off == series * N && p.orders[k].tau == tau) return p.orders[k].key_off;
+  for (size_t k = 0; k < p.orders.size(); ++k) {
+    const OrderJob& o = p.orders[k];
+    if (o.src_off == series * N && o.dims == key.dims &&
+        std::equal(key.lag, key.lag + 4, o.lag))
+      return o.key_off;
+  }
   const int64_t off = (int64_t)p.orders.size() * N;
-  p.orders.push_back({series * N, off, N, tau, 0});
+  OrderJob o{};
+  o.src_off = series * N;
+  o.key_off = off;
+  o.n = N;
+  o.dims = key.dims;
+  for (int d = 0; d < 4; ++d) o.lag[d] = key.lag[d];
+  p.orders.push_back(o);
   p.n_sets = (int32_t)p.orders.size();
   p.n_ord = p.n_sets * N;
   if (p.n_ord > (int64_t)INT32_MAX) fail(CCM_E_INVAL, "too many time points to order");
@@ -81,8 +102,9 @@ static void order_items(Plan& p) {
 // scan starts) and scanned in order, one snapshot per size.
 static Plan make_plan_nested(const Spec& s) {
   if (s.query_set != 0) fail(CCM_E_INVAL, "nested libraries predict every embedded point");
-  if (s.flags & (CCM_FLAG_TABLE | CCM_FLAG_PLAIN))
-    fail(CCM_E_INVAL, "nested libraries do not combine with the table or plain forms");
+  if (s.flags & (CCM_FLAG_TABLE | CCM_FLAG_PLAIN | CCM_FLAG_SHARED_E))
+    fail(CCM_E_INVAL,
+         "nested libraries do not combine with the table, plain or E-sweep-sharing forms");
   Plan p;
   p.spec = s;
   p.mode = excl_mode(s.excl);
@@ -119,7 +141,7 @@ static Plan make_plan_nested(const Spec& s) {
       for (int sr = 0; sr < 2; ++sr) {
         emb_off[sr] = p.n_emb;
         qord_off[sr] = p.n_qord;
-        ord_off[sr] = order_set(p, sr, E == 1 ? 0 : tau);
+        ord_off[sr] = order_set(p, sr, embedding_order(E, tau));
         p.embed.push_back({sr * N, p.n_emb, ord_off[sr], p.n_qord, ne, N, E, tau});
         p.n_emb += ne * E;
         p.n_qord += ne;
@@ -216,6 +238,122 @@ static Plan make_plan_nested(const Spec& s) {
   return p;
 }
 
+// E-sweep sharing: per tau, the embedding of E_max (the largest E asked for)
+// over N_c points, one library per (L, r) drawn over them, and one
+// realization per (L, r, direction) whose scan keeps a running list for
+// every E <= E_max (moments slots: E_max per tile, E's at slot_base +
+// (E-1) n_tiles); rz_fin holds one record per requested (E, L, r, direction).
+static Plan make_plan_shared(const Spec& s) {
+  if (s.query_set != 0) fail(CCM_E_INVAL, "E-sweep sharing predicts every embedded point");
+  if (s.flags & (CCM_FLAG_TABLE | CCM_FLAG_PLAIN | CCM_FLAG_NESTED))
+    fail(CCM_E_INVAL, "E-sweep sharing does not combine with the table, nested or plain forms");
+  Plan p;
+  p.spec = s;
+  p.mode = excl_mode(s.excl);
+  p.window = s.excl > 0 ? s.excl : 0;
+  const int nE = (int)s.E.size(), nT = (int)s.tau.size(), nL = (int)s.L.size();
+  const int64_t N = s.N;
+  const int32_t Emax = *std::max_element(s.E.begin(), s.E.end());
+  p.shared_emax = Emax;
+  p.n64 = 2 * N;
+  p.n32 = 2 * N;
+  p.ingest.push_back({0, 0, 2 * N});
+  const int64_t sorted_limit = gather_max_sorted_n_e();
+  p.n_out = 2LL * nE * nT * nL * s.r;
+  p.L_eff.assign((size_t)nE * nT * nL, 0);
+  const int64_t qt = (int64_t)kBlock * shared_queries_per_lane(Emax);
+  for (int it = 0; it < nT; ++it) {
+    const int32_t tau = s.tau[it];
+    const int64_t nc = N - (int64_t)(Emax - 1) * tau;
+    int64_t emb_off[2], qord_off[2], ord_off[2];
+    for (int sr = 0; sr < 2; ++sr) {
+      emb_off[sr] = p.n_emb;
+      qord_off[sr] = p.n_qord;
+      ord_off[sr] = order_set(p, sr, shared_order(Emax, tau));
+      p.embed.push_back({sr * N, p.n_emb, ord_off[sr], p.n_qord, nc, N, Emax, tau});
+      p.n_emb += nc * Emax;
+      p.n_qord += nc;
+      p.max_embed = std::max(p.max_embed, nc * Emax);
+    }
+    const int32_t sorted = nc <= sorted_limit ? 1 : 0;
+    if (sorted) p.max_sorted_n_e = std::max(p.max_sorted_n_e, nc);
+    for (int il = 0; il < nL; ++il) {
+      const int64_t le = std::min(s.L[il], nc);
+      for (int ie = 0; ie < nE; ++ie) p.L_eff[((size_t)ie * nT + it) * nL + il] = le;
+      for (int ri = 0; ri < s.r; ++ri) {
+        const int64_t lib_off = p.n_lib;
+        p.sample.push_back({s.seed, nc, le, lib_off, 0, tau, ri, 0});
+        p.n_lib += le;
+        for (int dir = 0; dir < 2; ++dir) {
+          const int lib_s = dir == 0 ? 1 : 0;
+          const int tgt_s = dir == 0 ? 0 : 1;
+          Realization R{};
+          R.emb_off = emb_off[lib_s];
+          R.pts_off = p.n_pts;
+          R.pj_off = p.n_pj;
+          R.qord_off = qord_off[lib_s];
+          R.tgt_off = tgt_s * N;
+          R.E = Emax;
+          R.tau = tau;
+          R.n_e = (int32_t)nc;
+          R.l_eff = (int32_t)le;
+          R.n_query = (int32_t)nc;
+          R.n_tiles = (int32_t)((nc + qt - 1) / qt);
+          R.slot_base = p.n_slots;
+          R.out_index = -1;
+          R.table_off = -1;
+          GatherJob gj{};
+          gj.emb_off = R.emb_off;
+          gj.lib_off = lib_off;
+          gj.order_off = ord_off[lib_s];
+          gj.pts_off = R.pts_off;
+          gj.pj_off = R.pj_off;
+          gj.start_off = R.slot_base * kWaves;
+          gj.l_eff = le;
+          gj.n_e = nc;
+          gj.n_series = N;
+          gj.E = Emax;
+          gj.tau = tau;
+          gj.qt = (int32_t)qt;
+          gj.query_set = 0;
+          gj.sorted = sorted;
+          p.gather.push_back(gj);
+          for (int ie = 0; ie < nE; ++ie) {
+            Realization F{};
+            F.slot_base = R.slot_base + (int64_t)(s.E[ie] - 1) * R.n_tiles;
+            F.n_tiles = R.n_tiles;
+            F.out_index = ((((int64_t)dir * nE + ie) * nT + it) * nL + il) * s.r + ri;
+            p.rz_fin.push_back(F);
+            p.preds += (double)nc;
+          }
+          p.n_pts += le * Emax;
+          p.n_pj += le;
+          p.n_slots += (int64_t)R.n_tiles * Emax;
+          p.rz.push_back(R);
+          p.rz_sample.push_back((int64_t)p.sample.size() - 1);
+          // each pair's E_max-coordinate distance is computed once
+          double pairs = (double)nc * (double)le;
+          if (p.mode == kExclSelf) pairs -= (double)le;
+          p.pairs += pairs;
+          p.flops += pairs * (3.0 * Emax - 1.0);
+        }
+      }
+    }
+  }
+  p.n_rho = (int64_t)p.rz_fin.size();
+  if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
+  order_items(p);
+  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
+                     p.n_sets, nullptr, nullptr));
+  p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
+                   p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
+                   (size_t)p.n_ord * 16 + p.n_slots * sizeof(Moments) + p.n_out * 8 +
+                   (p.rz.size() + p.rz_fin.size()) * sizeof(Realization) +
+                   p.items.size() * sizeof(Item) + p.sample.size() * sizeof(SampleJob) +
+                   p.gather.size() * sizeof(GatherJob);
+  return p;
+}
+
 // Validate a sweep and lay out every realization of it.
 Plan make_plan(const Spec& s) {
   if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
@@ -238,6 +376,7 @@ Plan make_plan(const Spec& s) {
       }
     }
   if (s.flags & CCM_FLAG_NESTED) return make_plan_nested(s);
+  if (s.flags & CCM_FLAG_SHARED_E) return make_plan_shared(s);
 
   Plan p;
   p.spec = s;
@@ -263,7 +402,7 @@ Plan make_plan(const Spec& s) {
       for (int sr = 0; sr < 2; ++sr) {
         emb_off[sr] = p.n_emb;
         qord_off[sr] = p.n_qord;
-        ord_off[sr] = order_set(p, sr, E == 1 ? 0 : tau);
+        ord_off[sr] = order_set(p, sr, embedding_order(E, tau));
         p.embed.push_back({sr * N, p.n_emb, ord_off[sr], p.n_qord, ne, N, E, tau});
         p.n_emb += ne * E;
         p.n_qord += ne;
@@ -356,8 +495,8 @@ Plan make_plan(const Spec& s) {
 // series; one realization per (searched series, L, r) predicting all others.
 Plan make_plan_matrix(const Spec& s) {
   if (s.M < 2) fail(CCM_E_INVAL, "M must be >= 2");
-  if (s.flags & CCM_FLAG_NESTED)
-    fail(CCM_E_INVAL, "nested libraries are not supported by the matrix form");
+  if (s.flags & (CCM_FLAG_NESTED | CCM_FLAG_SHARED_E))
+    fail(CCM_E_INVAL, "nested libraries and E-sweep sharing are not supported by the matrix form");
   if (s.N < 2) fail(CCM_E_INVAL, "N must be >= 2");
   if (s.L.empty()) fail(CCM_E_INVAL, "empty L list");
   if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
@@ -392,7 +531,7 @@ Plan make_plan_matrix(const Spec& s) {
   for (int a = 0; a < M; ++a) {
     emb_off[a] = p.n_emb;
     qord_off[a] = p.n_qord;
-    ord_off[a] = order_set(p, a, E == 1 ? 0 : tau);
+    ord_off[a] = order_set(p, a, embedding_order(E, tau));
     p.embed.push_back({a * N, p.n_emb, ord_off[a], p.n_qord, ne, N, E, tau});
     p.n_emb += ne * E;
     p.n_qord += ne;

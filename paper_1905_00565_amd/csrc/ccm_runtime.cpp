@@ -81,8 +81,8 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
     upload(ex->d_nested, p.nested);
     ex->d_scratch.ensure(p.n_scratch * 4);
     upload(ex->d_segs, p.segs);
-    upload(ex->d_rz_fin, p.rz_fin);
   }
+  if (!p.rz_fin.empty()) upload(ex->d_rz_fin, p.rz_fin);
   ex->d_s64.ensure(p.n64 * 8);
   ex->d_s32.ensure(p.n32 * 4);
   ex->d_iota.ensure(p.n_ord * 4);
@@ -172,7 +172,14 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
         ev = take_events(c);
         HIPCHK(hipEventRecord(ev.a, st));
       }
-      if (nested)
+      if (p.shared_emax > 0)
+        HIPCHK(launch_crossmap_shared(E, p.mode, grid, ex->d_rz.as<Realization>(),
+                                      ex->d_items.as<Item>() + p.e_first[E], n, next,
+                                      ex->d_emb.as<float>(), ex->d_pts.as<float>(),
+                                      ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
+                                      ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
+                                      ex->d_partial.as<Moments>(), p.window, st));
+      else if (nested)
         HIPCHK(launch_crossmap_nested(E, p.mode, grid, ex->d_rz.as<Realization>(),
                                       ex->d_items.as<Item>() + p.e_first[E], n, next,
                                       ex->d_emb.as<float>(), ex->d_pts.as<float>(),
@@ -253,7 +260,7 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                  (int64_t)p.rz.size(), p.spec.M, ex->d_partial.p,
                                  (int64_t)p.spec.L.size() * p.spec.r, ex->d_out.as<double>(),
                                  st));
-  else if (nested)
+  else if (!p.rz_fin.empty())
     HIPCHK(launch_finalize(ex->d_rz_fin.as<Realization>(), (int64_t)p.rz_fin.size(),
                            ex->d_partial.as<Moments>(), ex->d_out.as<double>(), st));
   else
@@ -538,7 +545,14 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
         d_gather, d_partial, d_out, d_nbr, d_d2, d_pred, d_iota, d_keys, d_keys_out, d_order,
         d_segoff, d_temp, d_qord, d_start, d_orders;
     std::vector<int32_t> seg{0, (int32_t)N};
-    std::vector<OrderJob> oj{{0, 0, N, E == 1 ? 0 : tau, 0}};
+    std::vector<OrderJob> oj(1);
+    {
+      const OrderKey key = embedding_order(E, tau);
+      oj[0] = OrderJob{};
+      oj[0].n = N;
+      oj[0].dims = key.dims;
+      for (int d = 0; d < 4; ++d) oj[0].lag[d] = key.lag[d];
+    }
     size_t temp_bytes = 0;
     HIPCHK(sort_series(nullptr, temp_bytes, nullptr, nullptr, nullptr, nullptr, N, 1,
                        nullptr, nullptr));

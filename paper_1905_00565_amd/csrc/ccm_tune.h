@@ -1,7 +1,8 @@
 // ccm_tune.h -- launch shape of the cross-map kernel for each embedding
 // dimension E (index 0 unused).  Written by paper_1905_00565_amd/autotune.py
 // from timings of the E = 1..10, tau = 1..5 sweep on coupled-logistic series
-// (N = 10000, r = 250 per (E, tau, L)); the build may override any table with -DCCM_TUNE_Q={...},
+// (N = 10000; r = 250 per (E, tau, L) for the kTune tables, r = 50 for the
+// kShared tables); the build may override any table with -DCCM_TUNE_Q={...},
 // -DCCM_TUNE_G={...} or -DCCM_TUNE_W={...} (the tuner does, to time
 // candidates).
 //
@@ -22,8 +23,25 @@
 #define CCM_TUNE_G {0, 16, 12, 8, 6, 6, 4, 3, 4, 4, 3}
 #endif
 
+// E-sweep sharing: the scan at E_max keeps E_max (E_max + 3) / 2 keys per
+// query, so its shape is chosen per E_max (index E_max):
+//   kSharedQ  queries per lane;  kSharedG  candidates per trigger check;
+//   kSharedW  minimum wavefronts per SIMD (0: free)
+#ifndef CCM_SHARED_Q
+#define CCM_SHARED_Q {0, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1}
+#endif
+#ifndef CCM_SHARED_G
+#define CCM_SHARED_G {0, 8, 8, 8, 8, 6, 6, 4, 4, 4, 4}
+#endif
+#ifndef CCM_SHARED_W
+#define CCM_SHARED_W {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 3}
+#endif
+
 namespace ccmk {
 constexpr int kTuneQ[11] = CCM_TUNE_Q;
 constexpr int kTuneG[11] = CCM_TUNE_G;
 constexpr int kTuneW[11] = CCM_TUNE_W;
+constexpr int kSharedQ[11] = CCM_SHARED_Q;
+constexpr int kSharedG[11] = CCM_SHARED_G;
+constexpr int kSharedW[11] = CCM_SHARED_W;
 }  // namespace ccmk

@@ -252,8 +252,11 @@ typedef struct {
 /* Start a server on the context's device (its own stream and thread). */
 ccm_status ccm_server_create(ccm_ctx *ctx, const ccm_server_cfg *cfg,
                              ccm_server **out);
-/* Queue a job; never waits for the GPU.  CCM_E_INVAL for a malformed job,
-   CCM_E_NOMEM if its footprint exceeds the whole budget. */
+/* Queue a job; never waits for the GPU.  CCM_E_INVAL for a malformed job
+   or one whose opts.flags ask for CCM_FLAG_NESTED or CCM_FLAG_SHARED_E (they
+   change the draws and are not served; the other flags choose an execution
+   form and are ignored), CCM_E_NOMEM if its footprint exceeds the whole
+   budget. */
 ccm_status ccm_submit(ccm_server *srv, const ccm_job *job, uint64_t *ticket);
 /* Wait until the job is finished (timeout_ns < 0: no limit).
    CCM_E_TIMEOUT if it is not finished in time, CCM_E_NOTFOUND for an unknown

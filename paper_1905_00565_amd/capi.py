@@ -319,14 +319,15 @@ def ccm_server_create(ctx, hbm_budget_bytes=0, max_jobs=0, epoch_target_ms=0.0):
     return h
 
 
-def ccm_submit(srv, X, Y, E, tau, L, r, seed, exclusion_radius=0, query_set=0, ctx=None):
+def ccm_submit(srv, X, Y, E, tau, L, r, seed, exclusion_radius=0, query_set=0, flags=0,
+               ctx=None):
     """Queue a job; returns its ticket.  Arrays are copied by the call."""
     X, Y = _f64(X), _f64(Y)
     if len(X) != len(Y):
         raise ValueError("X and Y must have the same length")
     Ls = np.ascontiguousarray(L, dtype=np.int64)
     job = ccm_job(_ptr(X), _ptr(Y), len(X), E, tau, _ptr(Ls), len(Ls), r,
-                  seed & (2**64 - 1), _opts(exclusion_radius, query_set, 0))
+                  seed & (2**64 - 1), _opts(exclusion_radius, query_set, flags))
     t = C.c_uint64()
     _check(ctx, lib().ccm_submit(srv, C.byref(job), C.byref(t)))
     return t.value

@@ -538,6 +538,10 @@ ccm_status ccm_submit(ccm_server* s, const ccm_job* job, uint64_t* ticket) {
   try {
     auto j = std::make_unique<Job>();
     if (!job->X || !job->Y) fail(CCM_E_INVAL, "NULL series");
+    // options that change the draws are not served; the others only choose
+    // an execution form, which the server picks itself
+    if (job->opts.flags & (CCM_FLAG_NESTED | CCM_FLAG_SHARED_E))
+      fail(CCM_E_INVAL, "nested libraries and E-sweep sharing are not served");
     Spec sp = make_spec(job->N, &job->E, 1, &job->tau, 1, job->L, job->nL, job->r, job->seed,
                         &job->opts);
     sp.flags = 0;

@@ -125,6 +125,10 @@ def test_server_malformed_timeout_cancel(ctx):
         assert ei.value.status == capi.CCM_E_INVAL
         with pytest.raises(capi.CCMError):
             srv.submit(x, y, 2, 1, [3], 2, 1)            # L < E + 2
+        for flag in (capi.CCM_FLAG_NESTED, capi.CCM_FLAG_SHARED_E):   # other draws: not served
+            with pytest.raises(capi.CCMError) as ei:
+                srv.submit(x, y, 2, 1, [100], 2, 1, flags=flag)
+            assert ei.value.status == capi.CCM_E_INVAL
         long_t = srv.submit(x, y, 8, 1, [5000, 39993], 20, 3)
         assert srv.wait(long_t, 0) == capi.CCM_E_TIMEOUT
         queued = srv.submit(x[:500], y[:500], 2, 1, [50, 499], 3, 4)   # waits: max_jobs=1

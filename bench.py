@@ -411,7 +411,8 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(the cross map shards by realization, see the design notes)", flush=True)
+              "(the cross map would shard by realization: each GPU its own share of the "
+              "(E, tau, L, r) realizations, rho gathered at the end)", flush=True)
         sys.exit(2)
     import torch
 

@@ -170,3 +170,21 @@ def test_shared_e_long_series_sample(ctx, orc):
     assert np.all(np.isfinite(got)) and np.all(np.abs(got) <= 1.0)
     want, _ = oracle_sweep(orc, w.X, w.Y, E, [2], L, 1, w.seed)
     rho_close(got, want)
+
+
+def test_shared_e_full_sweep_sampled(ctx, orc):
+    """The bench's shared-E call in full (N = 10^4, E = 1..10, tau = 1..5, 20 L,
+    r = 250): sampled (tau, L) entries of its first two realizations against
+    the oracle (a realization's library depends on its index, not on r); every
+    value finite and within [-1, 1]."""
+    w = synth.workload_sweep()
+    got = ctx.ccm_sweep(w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed, flags=SHARED)
+    assert got.shape == (2, 10, 5, len(w.L), w.r)
+    assert np.all(np.isfinite(got)) and np.all(np.abs(got) <= 1.0)
+    picks = [(0, 0), (2, 9), (4, 13), (1, 15)]      # (tau index, L index)
+    with ThreadPoolExecutor(max_workers=len(picks)) as ex:
+        outs = list(ex.map(lambda p: orc.ccm_shared_e(w.X, w.Y, w.E, w.tau[p[0]], [w.L[p[1]]],
+                                                       2, w.seed), picks))
+    for (it, il), (rxy, ryx, _) in zip(picks, outs):
+        rho_close(got[0, :, it, il, :2], rxy[:, 0, :])
+        rho_close(got[1, :, it, il, :2], ryx[:, 0, :])

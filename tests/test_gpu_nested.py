@@ -5,6 +5,8 @@ within 1e-5 of the oracle (the build's tolerance) for every library size,
 including sizes that clamp to N_e and unsorted L lists; the batched forms
 agree bit for bit among themselves; invalid combinations are rejected.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -117,3 +119,20 @@ def test_nested_work_and_invalid(ctx):
     with pytest.raises(capi.CCMError) as ei:
         ctx.ccm_matrix(S, 2, 1, [100], 2, 3, flags=NESTED)
     assert ei.value.status == capi.CCM_E_INVAL
+
+
+def test_nested_full_sweep_sampled(ctx, orc):
+    """The bench's nested call in full (N = 10^4, E = 1..10, tau = 1..5, 20 L,
+    r = 250): sampled (E, tau) entries of its first two realizations at two
+    library sizes against the oracle (an ordering depends on (seed, E, tau,
+    r index) only, and a library is its prefix whatever the other sizes)."""
+    w = synth.workload_sweep()
+    got = ctx.ccm_sweep(w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed, flags=NESTED)
+    assert np.all(np.isfinite(got)) and np.all(np.abs(got) <= 1.0)
+    picks = [(0, 0, (0, 19)), (3, 2, (5, 12)), (9, 4, (1, 8)), (6, 1, (10, 14))]
+    with ThreadPoolExecutor(max_workers=len(picks)) as ex:
+        outs = list(ex.map(lambda p: orc.ccm_nested(w.X, w.Y, w.E[p[0]], w.tau[p[1]],
+                                                    [w.L[i] for i in p[2]], 2, w.seed), picks))
+    for (ie, it, ils), (oxy, oyx, _) in zip(picks, outs):
+        rho_close(got[0, ie, it, list(ils), :2], oxy)
+        rho_close(got[1, ie, it, list(ils), :2], oyx)

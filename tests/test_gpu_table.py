@@ -130,3 +130,13 @@ def test_table_long_series_sample(ctx):
     b = ctx.ccm(w.X, w.Y, 3, 2, L, 2, w.seed, flags=TABLE)
     for u, v in zip(a[:2], b[:2]):
         assert bitwise_equal(u, v)
+
+
+def test_table_full_sweep_bitwise(ctx):
+    """The bench's sweep in full (N = 10^4, E = 1..10, tau = 1..5, 20 L,
+    r = 250) through the tables equals the brute-force sweep bit for bit."""
+    w = synth.workload_sweep()
+    a, pa = sweep(ctx, w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed)
+    b, pb = sweep(ctx, w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed, flags=TABLE)
+    assert pb["table_realizations"] > 0.5 * pb["realizations"]
+    assert bitwise_equal(a, b)

@@ -188,3 +188,22 @@ def test_shared_e_full_sweep_sampled(ctx, orc):
     for (it, il), (rxy, ryx, _) in zip(picks, outs):
         rho_close(got[0, :, it, il, :2], rxy[:, 0, :])
         rho_close(got[1, :, it, il, :2], ryx[:, 0, :])
+
+
+def test_shared_e_minimum_sizes_and_constant_series(ctx, orc):
+    """Boundaries: N_c = E_max + 2 at the largest tau (N = 42, E_max = 4,
+    tau = 12) with L at the minimum and clamped; a constant series, whose
+    predictions have no variance (rho NaN where the oracle's is)."""
+    rng = np.random.default_rng(42)
+    X, Y = synth.coupled_logistic(42, *rng.uniform(0.1, 0.9, 2))
+    E, tau, L = [1, 2, 4], [1, 12], [6, 40]
+    got = ctx.ccm_sweep(X, Y, E, tau, L, 3, 7, flags=SHARED)
+    want, le = oracle_sweep(orc, X, Y, E, tau, L, 3, 7)
+    assert le[1].tolist() == [6, 6]
+    rho_close(got, want)
+    C = np.full(300, 0.25)
+    Z = rng.standard_normal(300)
+    got = ctx.ccm_sweep(C, Z, [1, 3], [2], [50, 296], 2, 9, flags=SHARED)
+    want, _ = oracle_sweep(orc, C, Z, [1, 3], [2], [50, 296], 2, 9)
+    assert np.isnan(want).any()
+    rho_close(got, want)

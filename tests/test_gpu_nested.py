@@ -136,3 +136,23 @@ def test_nested_full_sweep_sampled(ctx, orc):
     for (ie, it, ils), (oxy, oyx, _) in zip(picks, outs):
         rho_close(got[0, ie, it, list(ils), :2], oxy)
         rho_close(got[1, ie, it, list(ils), :2], oyx)
+
+
+def test_nested_minimum_sizes_and_constant_series(ctx, orc):
+    """Boundaries: N_e = E + 2 (N = 42, E = 4, tau = 12) with L at the
+    minimum and clamped (one segment); a constant series, whose predictions
+    have no variance (rho NaN where the oracle's is)."""
+    rng = np.random.default_rng(43)
+    X, Y = synth.coupled_logistic(42, *rng.uniform(0.1, 0.9, 2))
+    gxy, gyx, gle = ctx.ccm(X, Y, 4, 12, [6, 40], 3, 7, flags=NESTED)
+    oxy, oyx, ole = orc.ccm_nested(X, Y, 4, 12, [6, 40], 3, 7)
+    assert gle.tolist() == ole.tolist() == [6, 6]
+    rho_close(gxy, oxy)
+    rho_close(gyx, oyx)
+    C = np.full(300, 0.25)
+    Z = rng.standard_normal(300)
+    gxy, gyx, _ = ctx.ccm(C, Z, 3, 2, [50, 296], 2, 9, flags=NESTED)
+    oxy, oyx, _ = orc.ccm_nested(C, Z, 3, 2, [50, 296], 2, 9)
+    assert np.isnan(oxy).any() or np.isnan(oyx).any()
+    rho_close(gxy, oxy)
+    rho_close(gyx, oyx)

@@ -101,7 +101,7 @@ typedef struct {
    and any wavefront whose walk runs off the end of its rows, scan by brute
    force.  Neighbours, predictions and rho are bitwise identical to the
    brute-force path.  Costs n_e * CCM_TABLE_WIDTH * 4 bytes of device memory
-   per table.  Not supported by the served form (ignored there). */
+   per table.  Honoured by the served form too (ccm_submit). */
 #define CCM_FLAG_TABLE 8u
 #define CCM_TABLE_WIDTH 1024
 /* Nested libraries (an option of this library, not of the paper): the
@@ -254,9 +254,10 @@ ccm_status ccm_server_create(ccm_ctx *ctx, const ccm_server_cfg *cfg,
                              ccm_server **out);
 /* Queue a job; never waits for the GPU.  CCM_E_INVAL for a malformed job
    or one whose opts.flags ask for CCM_FLAG_NESTED or CCM_FLAG_SHARED_E (they
-   change the draws and are not served; the other flags choose an execution
-   form and are ignored), CCM_E_NOMEM if its footprint exceeds the whole
-   budget. */
+   change the draws and are not served), CCM_E_NOMEM if its footprint (tables
+   included) exceeds the whole budget.  CCM_FLAG_TABLE is honoured; the other
+   flags choose an execution form, which the server picks itself, and are
+   ignored. */
 ccm_status ccm_submit(ccm_server *srv, const ccm_job *job, uint64_t *ticket);
 /* Wait until the job is finished (timeout_ns < 0: no limit).
    CCM_E_TIMEOUT if it is not finished in time, CCM_E_NOTFOUND for an unknown

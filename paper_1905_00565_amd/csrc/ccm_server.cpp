@@ -76,8 +76,8 @@ enum JobState { kPending, kActive, kDone, kCancelled, kFailed };
 
 // Byte layout of one job's region in the arena.
 struct Layout {
-  uint64_t s64, s32, iota, keys, keys_out, order, temp, qord, emb, lib, pts, pj, out;
-  uint64_t d_ingest, d_embed, d_sample, d_gather, d_segoff, d_orders;
+  uint64_t s64, s32, iota, keys, keys_out, order, temp, qord, emb, lib, pts, pj, out, table;
+  uint64_t d_ingest, d_embed, d_sample, d_gather, d_segoff, d_orders, d_tables;
   uint64_t bytes;
 };
 
@@ -104,12 +104,14 @@ Layout layout_of(const Plan& p) {
   l.pts = take(p.n_pts * 4);
   l.pj = take(p.n_pj * 4);
   l.out = take(p.n_out * 8);
+  l.table = take(p.n_table * 4);
   l.d_ingest = take(p.ingest.size() * sizeof(IngestJob));
   l.d_embed = take(p.embed.size() * sizeof(EmbedJob));
   l.d_sample = take(p.sample.size() * sizeof(SampleJob));
   l.d_gather = take(p.gather.size() * sizeof(GatherJob));
   l.d_segoff = take(p.seg_off.size() * 4);
   l.d_orders = take(p.orders.size() * sizeof(OrderJob));
+  l.d_tables = take(p.tables.size() * sizeof(TableJob));
   l.bytes = o;
   return l;
 }
@@ -232,7 +234,23 @@ void start_job(ccm_server* s, Job& j) {
     R.qord_off += (int64_t)((R0 + L.qord) / 4);
     R.tgt_off += (int64_t)((R0 + L.s64) / 8);
     R.slot_base += (int64_t)j.slot0;
+    if (R.table_off >= 0) R.table_off += (int64_t)((R0 + L.table) / 4);
   }
+  // distance indexing tables, rebased the same way; every table must lie in
+  // the job's region (its rows and the embedding they are built from)
+  std::vector<TableJob> tj = p.tables;
+  const int64_t emb_lo = (int64_t)((R0 + L.emb) / 4), emb_hi = emb_lo + p.n_emb;
+  const int64_t tab_lo = (int64_t)((R0 + L.table) / 4), tab_hi = tab_lo + p.n_table;
+  for (auto& t : tj) {
+    t.emb_off += emb_lo;
+    t.out_off += tab_lo;
+    if (t.emb_off < emb_lo || t.emb_off + (int64_t)t.n_e * t.E > emb_hi || t.out_off < tab_lo ||
+        t.out_off + (int64_t)t.n_e * table_row_stride(t.w) > tab_hi)
+      fail(CCM_E_DEVICE, "table layout outside the job's region");
+  }
+  for (const auto& R : rz)
+    if (R.table_off >= 0 && (R.table_off < tab_lo || R.table_off >= tab_hi))
+      fail(CCM_E_DEVICE, "table offset outside the job's region");
   HIPCHK(hipMemcpy(at<char>(s, R0 + L.s64), j.X.data(), N * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(at<char>(s, R0 + L.s64) + N * 8, j.Y.data(), N * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_ingest), p.ingest.data(),
@@ -249,6 +267,9 @@ void start_job(ccm_server* s, Job& j) {
                    p.orders.size() * sizeof(OrderJob), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(s->rz_table.as<Realization>() + j.rz0, rz.data(),
                    rz.size() * sizeof(Realization), hipMemcpyHostToDevice));
+  if (!tj.empty())
+    HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_tables), tj.data(), tj.size() * sizeof(TableJob),
+                     hipMemcpyHostToDevice));
   j.X.clear();
   j.X.shrink_to_fit();
   j.Y.clear();
@@ -258,6 +279,10 @@ void start_job(ccm_server* s, Job& j) {
                        at<double>(s, R0 + L.s64), at<float>(s, R0 + L.s32), st));
   HIPCHK(launch_embed(at<EmbedJob>(s, R0 + L.d_embed), (int)p.embed.size(), p.max_embed,
                       at<float>(s, R0 + L.s32), at<float>(s, R0 + L.emb), st));
+  for (int E = 1; E <= kMaxE; ++E)
+    HIPCHK(launch_table_build(E, at<TableJob>(s, R0 + L.d_tables) + p.te_first[E],
+                              p.te_count[E], p.te_max_ne[E], at<float>(s, 0),
+                              at<int32_t>(s, 0), st));
   HIPCHK(launch_order_keys(at<OrderJob>(s, R0 + L.d_orders), p.n_sets,
                            at<float>(s, R0 + L.s32), at<uint32_t>(s, R0 + L.keys), st));
   HIPCHK(launch_iota_segments(at<int32_t>(s, R0 + L.iota), N, p.n_sets, st));
@@ -360,6 +385,7 @@ void scheduler_loop(ccm_server* s) {
       const double budget = s->epoch_ms * s->lane_ops_per_ms;
       double cost = 0.0;
       std::map<GroupKey, std::vector<Item>> groups;
+      std::map<GroupKey, int> group_table_ne;   // largest n_e a group's items walk
       std::vector<Job*> completes;
       size_t n_items = 0;
       for (uint64_t t : s->active) {
@@ -370,6 +396,8 @@ void scheduler_loop(ccm_server* s) {
         const int qt = kBlock * crossmap_queries_per_lane(E, false);
         const GroupKey key{E, p.mode, p.spec.query_set, p.window};
         auto& g = groups[key];
+        int& tne = group_table_ne[key];
+        tne = std::max(tne, p.e_table_ne[E]);
         while (j.next_item < p.items.size() &&
                (cost < budget || n_items < s->min_items) && n_items < s->items_cap) {
           const Item it = p.items[j.next_item++];
@@ -432,7 +460,7 @@ void scheduler_loop(ccm_server* s) {
                                s->items_dev[buf].as<Item>() + pos, n, nullptr, fa, fa, ia, ia,
                                s->slots_start.as<int32_t>(), da,
                                s->slots_partial.as<Moments>(), kv.first.qs, kv.first.window,
-                               nodump, nullptr, 0, es));
+                               nodump, ia, group_table_ne[kv.first], es));
         pos += n;
       }
       HIPCHK(hipEventRecord(s->epoch_ev[buf], es));
@@ -544,7 +572,7 @@ ccm_status ccm_submit(ccm_server* s, const ccm_job* job, uint64_t* ticket) {
       fail(CCM_E_INVAL, "nested libraries and E-sweep sharing are not served");
     Spec sp = make_spec(job->N, &job->E, 1, &job->tau, 1, job->L, job->nL, job->r, job->seed,
                         &job->opts);
-    sp.flags = 0;
+    sp.flags &= CCM_FLAG_TABLE;   // execution forms are the server's; tables keep results
     check_host_series(job->X, job->N, "X");
     check_host_series(job->Y, job->N, "Y");
     j->plan = make_plan(sp);

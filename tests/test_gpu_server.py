@@ -1,8 +1,9 @@
 """Served form: continuous batching of jobs, admission by HBM footprint.
 
 Every job's rho must be bitwise equal to the same job run alone through
-ccm() (and within 1e-5 of the oracle); failure paths are forced from the
-host (a budget too small, a malformed job, a zero timeout, a cancel).
+ccm() (and within 1e-5 of the oracle), with or without distance indexing
+tables; failure paths are forced from the host (a budget too small, a
+malformed job, options that are not served, a zero timeout, a cancel).
 """
 import numpy as np
 import pytest
@@ -155,3 +156,21 @@ def test_server_destroy_with_work_outstanding(ctx):
     # the context is still usable afterwards
     rxy, _, _ = ctx.ccm(x[:400], y[:400], 2, 1, [50], 2, 1)
     assert np.isfinite(rxy).all()
+
+
+def test_server_table_jobs_bitwise(ctx):
+    """Jobs with CCM_FLAG_TABLE served beside jobs without: every job's rho
+    bitwise equal to the same job alone without tables (the walk selects the
+    scan's neighbours)."""
+    jobs = make_jobs(6, seed=7, n_lo=2000, n_hi=6000, r=3)
+    with capi.Server(ctx, epoch_target_ms=2.0) as srv:
+        tickets = [srv.submit(j["X"], j["Y"], j["E"], j["tau"], j["L"], j["r"], j["seed"],
+                              flags=capi.CCM_FLAG_TABLE if k % 2 == 0 else 0)
+                   for k, j in enumerate(jobs)]
+        for t in tickets:
+            assert srv.wait(t) == capi.CCM_OK
+        out = [srv.result(t, len(j["L"]), j["r"]) for t, j in zip(tickets, jobs)]
+    for (rxy, ryx, _), j in zip(out, jobs):
+        axy, ayx, _ = run_alone(ctx, j)
+        assert np.array_equal(rxy, axy, equal_nan=True)
+        assert np.array_equal(ryx, ayx, equal_nan=True)

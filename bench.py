@@ -344,22 +344,24 @@ def served_leg(ctx, n_jobs, load, seed=4):
     """Served form on the job-stream workload: capacity from a closed loop
     (all jobs submitted at once), then an open loop of Poisson arrivals at
     `load` x capacity for p50/p99 latency.  Comparisons: the same jobs one
-    after another through ccm() (each call batched), and the first few
-    through ccm() with one launch per realization (the unbatched form)."""
+    after another through ccm() (each call batched), the first few through
+    ccm() with one launch per realization (the unbatched form), and the
+    closed loop again with distance indexing tables (same results)."""
     stream = synth.job_stream(n_jobs, 1.0, seed=seed)
     jobs = []
     for j in stream:
         X, Y = j["make"]()
         jobs.append((X, Y, j))
 
-    def run(srv, arrivals):
+    def run(srv, arrivals, flags=0):
         t0 = time.perf_counter()
         tickets = []
         for (X, Y, j), ta in zip(jobs, arrivals):
             delay = ta - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            tickets.append((srv.submit(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"]), j))
+            tickets.append((srv.submit(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"],
+                                       flags=flags), j))
         lat, preds = [], 0.0
         for t, j in tickets:
             assert srv.wait(t) == capi.CCM_OK
@@ -376,6 +378,7 @@ def served_leg(ctx, n_jobs, load, seed=4):
         gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n_jobs)
         arrivals = np.cumsum(gaps) - gaps[0]
         make_open, lat_open, _ = run(srv, list(arrivals))
+        make_tables, _, _ = run(srv, [0.0] * n_jobs, flags=capi.CCM_FLAG_TABLE)
     per_job = []
     for X, Y, j in jobs:
         t0 = time.perf_counter()
@@ -400,6 +403,8 @@ def served_leg(ctx, n_jobs, load, seed=4):
         "open_loop_jobs_per_sec": n_jobs / make_open,
         "fifo_ccm_jobs_per_sec": n_jobs / fifo,
         "served_over_fifo": (n_jobs / make_closed) / (n_jobs / fifo),
+        "capacity_jobs_per_sec_with_tables": n_jobs / make_tables,
+        "tables_over_scan": make_closed / make_tables,
         "plain_subset_jobs": n_plain,
         "plain_subset_seconds": fifo_plain,
         "batched_subset_seconds": sum(per_job[:n_plain]),

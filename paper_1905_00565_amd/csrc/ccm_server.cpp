@@ -236,21 +236,13 @@ void start_job(ccm_server* s, Job& j) {
     R.slot_base += (int64_t)j.slot0;
     if (R.table_off >= 0) R.table_off += (int64_t)((R0 + L.table) / 4);
   }
-  // distance indexing tables, rebased the same way; every table must lie in
-  // the job's region (its rows and the embedding they are built from)
+  // distance indexing tables, rebased the same way (their extents within
+  // the job's embedding and table pools were checked at submit)
   std::vector<TableJob> tj = p.tables;
-  const int64_t emb_lo = (int64_t)((R0 + L.emb) / 4), emb_hi = emb_lo + p.n_emb;
-  const int64_t tab_lo = (int64_t)((R0 + L.table) / 4), tab_hi = tab_lo + p.n_table;
   for (auto& t : tj) {
-    t.emb_off += emb_lo;
-    t.out_off += tab_lo;
-    if (t.emb_off < emb_lo || t.emb_off + (int64_t)t.n_e * t.E > emb_hi || t.out_off < tab_lo ||
-        t.out_off + (int64_t)t.n_e * table_row_stride(t.w) > tab_hi)
-      fail(CCM_E_DEVICE, "table layout outside the job's region");
+    t.emb_off += (int64_t)((R0 + L.emb) / 4);
+    t.out_off += (int64_t)((R0 + L.table) / 4);
   }
-  for (const auto& R : rz)
-    if (R.table_off >= 0 && (R.table_off < tab_lo || R.table_off >= tab_hi))
-      fail(CCM_E_DEVICE, "table offset outside the job's region");
   HIPCHK(hipMemcpy(at<char>(s, R0 + L.s64), j.X.data(), N * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(at<char>(s, R0 + L.s64) + N * 8, j.Y.data(), N * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_ingest), p.ingest.data(),
@@ -576,6 +568,16 @@ ccm_status ccm_submit(ccm_server* s, const ccm_job* job, uint64_t* ticket) {
     check_host_series(job->X, job->N, "X");
     check_host_series(job->Y, job->N, "Y");
     j->plan = make_plan(sp);
+    // every table lies in the job's pools (its rows, and the embedding its
+    // rows are built from), so that rebasing keeps it in the job's region
+    const Plan& p = j->plan;
+    for (const TableJob& t : p.tables)
+      if (t.emb_off < 0 || t.emb_off + (int64_t)t.n_e * t.E > p.n_emb || t.out_off < 0 ||
+          t.out_off + (int64_t)t.n_e * table_row_stride(t.w) > p.n_table)
+        fail(CCM_E_INVAL, "internal: a table outside the job's pools");
+    for (const Realization& R : p.rz)
+      if (R.table_off >= 0 && R.table_off >= p.n_table)
+        fail(CCM_E_INVAL, "internal: a table offset outside the job's pools");
     j->lay = layout_of(j->plan);
     if (j->lay.bytes > s->arena_alloc.capacity() ||
         (uint64_t)j->plan.n_slots > s->slot_alloc.capacity() ||

@@ -1533,7 +1533,7 @@ __global__ __launch_bounds__(kBlock) void k_crossmap_multi(
 // diagonal and when either side is constant.
 template <int E, int Q, int MODE>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(kTuneW[E] > 0 ? kTuneW[E] : 1, 8))) void k_crossmap_nested(
+__attribute__((amdgpu_waves_per_eu(kNestedW[E] > 0 ? kNestedW[E] : 1, 8))) void k_crossmap_nested(
     const Realization* __restrict__ rzs, const Item* __restrict__ items,
     int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
     const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,

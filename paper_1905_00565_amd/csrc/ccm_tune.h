@@ -37,7 +37,16 @@
 #define CCM_SHARED_W {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 3}
 #endif
 
+// Nested libraries: minimum wavefronts per SIMD of the segmented scan (it
+// keeps more state live than the plain scan, so a lower minimum than the
+// plain scan's spills less; timed at r = 50 against no minimum and 4, 5 and
+// the plain scan's table; 0: free).
+#ifndef CCM_NESTED_W
+#define CCM_NESTED_W {0, 7, 6, 4, 4, 4, 5, 4, 4, 4, 4}
+#endif
+
 namespace ccmk {
+constexpr int kNestedW[11] = CCM_NESTED_W;
 constexpr int kTuneQ[11] = CCM_TUNE_Q;
 constexpr int kTuneG[11] = CCM_TUNE_G;
 constexpr int kTuneW[11] = CCM_TUNE_W;

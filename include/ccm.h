@@ -261,13 +261,18 @@ ccm_status ccm_server_create(ccm_ctx *ctx, const ccm_server_cfg *cfg,
 ccm_status ccm_submit(ccm_server *srv, const ccm_job *job, uint64_t *ticket);
 /* Wait until the job is finished (timeout_ns < 0: no limit).
    CCM_E_TIMEOUT if it is not finished in time, CCM_E_NOTFOUND for an unknown
-   or cancelled ticket, the job's error status if it failed. */
+   or cancelled ticket, the job's error status if it failed.  A job cancelled
+   while running counts as finished once its in-flight device work is done. */
 ccm_status ccm_wait(ccm_server *srv, uint64_t ticket, int64_t timeout_ns);
 /* Copy a finished job's rho (host double[nL][r] each, nullable) and stats,
-   and release the ticket.  CCM_E_BUSY while the job is still running. */
+   and release the ticket.  CCM_E_BUSY while the job is still running, also
+   when it was cancelled and its in-flight device work is not done yet (the
+   ticket is then kept); CCM_E_NOTFOUND, releasing the ticket, for a job
+   cancelled and finished. */
 ccm_status ccm_result(ccm_server *srv, uint64_t ticket, double *rho_X_from_MY,
                       double *rho_Y_from_MX, ccm_job_stats *stats);
-/* Cancel a queued or running job (its remaining work is skipped). */
+/* Cancel a queued or running job (its remaining work is skipped; work
+   already on the device completes before the job is released). */
 ccm_status ccm_cancel(ccm_server *srv, uint64_t ticket);
 /* Cancel everything outstanding, wait for the device, release the server. */
 void ccm_server_destroy(ccm_server *srv);

@@ -129,6 +129,11 @@ struct Job {
   size_t next_item = 0;          // scheduling cursor into plan.items
   int64_t last_epoch = -1;       // last epoch that ran items of this job
   bool finishing = false;        // finalize queued
+  // Set only once the scheduler holds no reference to the job any more (its
+  // device work is complete and its resources are released, or it never
+  // left the queue): until then ccm_wait keeps waiting and ccm_result
+  // answers CCM_E_BUSY, whatever the state says.
+  bool retired = false;
   hipEvent_t done_ev = nullptr;
   double* rho_host = nullptr;    // pinned [n_out]
   double t_submit = 0, t_admit = 0, t_done = 0;
@@ -331,6 +336,7 @@ void scheduler_loop(ccm_server* s) {
           j.state = (j.state == kCancelled) ? kCancelled : kDone;
           j.t_done = s->now();
           free_job_resources(s, j);
+          j.retired = true;
           it = s->active.erase(it);
           s->cv_done.notify_all();
         } else {
@@ -385,7 +391,7 @@ void scheduler_loop(ccm_server* s) {
         if (j.finishing || j.state == kCancelled) continue;
         const Plan& p = j.plan;
         const int E = p.spec.E[0];
-        const int qt = kBlock * crossmap_queries_per_lane(E, false);
+        const int qt = kBlock * crossmap_queries_per_lane(E);
         const GroupKey key{E, p.mode, p.spec.query_set, p.window};
         auto& g = groups[key];
         int& tne = group_table_ne[key];
@@ -447,7 +453,7 @@ void scheduler_loop(ccm_server* s) {
       for (auto& kv : groups) {
         const int n = (int)kv.second.size();
         if (n == 0) continue;
-        HIPCHK(launch_crossmap(kv.first.E, kv.first.mode, false, n,
+        HIPCHK(launch_crossmap(kv.first.E, kv.first.mode, n,
                                s->rz_table.as<Realization>(),
                                s->items_dev[buf].as<Item>() + pos, n, nullptr, fa, fa, ia, ia,
                                s->slots_start.as<int32_t>(), da,
@@ -470,12 +476,14 @@ void scheduler_loop(ccm_server* s) {
         j.status = e.status;
         j.t_done = s->now();
         free_job_resources(s, j);
+        j.retired = true;
       }
       s->active.clear();
       for (uint64_t t : s->pending) {
         Job& j = *s->jobs[t];
         j.state = kFailed;
         j.status = e.status;
+        j.retired = true;
       }
       s->pending.clear();
       s->cv_done.notify_all();
@@ -613,7 +621,7 @@ ccm_status ccm_wait(ccm_server* s, uint64_t ticket, int64_t timeout_ns) {
   auto it = s->jobs.find(ticket);
   if (it == s->jobs.end()) return CCM_E_NOTFOUND;
   Job* j = it->second.get();
-  auto done = [&] { return j->state == kDone || j->state == kCancelled || j->state == kFailed; };
+  auto done = [&] { return j->retired; };
   if (timeout_ns < 0) {
     s->cv_done.wait(lk, done);
   } else if (!s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done)) {
@@ -630,8 +638,9 @@ ccm_status ccm_result(ccm_server* s, uint64_t ticket, double* rho_xy, double* rh
     std::lock_guard<std::mutex> lock(s->mu);
     auto it = s->jobs.find(ticket);
     if (it == s->jobs.end()) return CCM_E_NOTFOUND;
-    const JobState st = it->second->state;
-    if (st == kPending || st == kActive) return CCM_E_BUSY;
+    // a cancelled job that is still active has device work in flight and
+    // is still referenced by the scheduler: it is released only once retired
+    if (!it->second->retired) return CCM_E_BUSY;
     j = std::move(it->second);
     s->jobs.erase(it);
   }
@@ -667,6 +676,7 @@ ccm_status ccm_cancel(ccm_server* s, uint64_t ticket) {
     s->pending.erase(std::find(s->pending.begin(), s->pending.end(), ticket));
     j.state = kCancelled;
     j.t_done = s->now();
+    j.retired = true;
     s->cv_done.notify_all();
   } else if (j.state == kActive) {
     j.state = kCancelled;   // remaining items are skipped; resources freed when idle
@@ -680,7 +690,10 @@ void ccm_server_destroy(ccm_server* s) {
   {
     std::lock_guard<std::mutex> lock(s->mu);
     s->stop = true;
-    for (uint64_t t : s->pending) s->jobs[t]->state = kCancelled;
+    for (uint64_t t : s->pending) {
+      s->jobs[t]->state = kCancelled;
+      s->jobs[t]->retired = true;
+    }
     s->pending.clear();
     for (uint64_t t : s->active) s->jobs[t]->state = kCancelled;
     s->cv_work.notify_all();

@@ -5,6 +5,8 @@ ccm() (and within 1e-5 of the oracle), with or without distance indexing
 tables; failure paths are forced from the host (a budget too small, a
 malformed job, options that are not served, a zero timeout, a cancel).
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -54,7 +56,7 @@ def test_server_single_job_bitwise_and_oracle(ctx):
     assert st["realizations"] == 2 * len(j["L"]) * j["r"]
 
 
-def test_server_mix_equals_alone(ctx):
+def test_server_mix_equals_alone(ctx, orc):
     jobs = make_jobs(14, seed=2)
     with capi.Server(ctx, epoch_target_ms=2.0) as srv:
         tickets = [srv.submit(j["X"], j["Y"], j["E"], j["tau"], j["L"], j["r"], j["seed"])
@@ -68,6 +70,9 @@ def test_server_mix_equals_alone(ctx):
         axy, ayx, _ = run_alone(ctx, j)
         assert np.array_equal(rxy, axy, equal_nan=True)
         assert np.array_equal(ryx, ayx, equal_nan=True)
+        # every rho of every job of the mix against the oracle
+        oxy, oyx = orc.ccm_threaded(j["X"], j["Y"], j["E"], j["tau"], j["L"], j["r"], j["seed"])
+        assert np.max(np.abs(rxy - oxy)) < 1e-5 and np.max(np.abs(ryx - oyx)) < 1e-5
         spans.append((st["t_admit"], st["t_done"]))
     # continuous batching: some jobs were on the device at the same time
     overlaps = sum(1 for a in range(len(spans)) for b in range(a + 1, len(spans))
@@ -174,3 +179,66 @@ def test_server_table_jobs_bitwise(ctx):
         axy, ayx, _ = run_alone(ctx, j)
         assert np.array_equal(rxy, axy, equal_nan=True)
         assert np.array_equal(ryx, ayx, equal_nan=True)
+
+
+def test_server_cancel_running_job(ctx):
+    """Cancel a job while its work is on the device, then wait for it and
+    collect it: the ticket stays busy until the in-flight work retires (the
+    scheduler still holds the job), wait then reports it cancelled, and jobs
+    submitted afterwards run to the same results as alone."""
+    x, y = synth.coupled_logistic(50000)
+    with capi.Server(ctx, epoch_target_ms=5.0) as srv:
+        # about 2e12 pairs: long enough to be mid-flight after 0.15 s
+        big = srv.submit(x, y, 8, 1, [20000, 30000, 49993], 200, 3)
+        time.sleep(0.15)
+        assert srv.wait(big, 0) == capi.CCM_E_TIMEOUT
+        assert srv.cancel(big) == capi.CCM_OK
+        try:
+            srv.result(big, 3, 200)
+            early = capi.CCM_OK
+        except capi.CCMError as e:
+            early = e.status
+        # busy while retiring; unknown once retired and released by this call
+        assert early in (capi.CCM_E_BUSY, capi.CCM_E_NOTFOUND)
+        assert srv.wait(big) == capi.CCM_E_NOTFOUND
+        with pytest.raises(capi.CCMError) as ei:
+            srv.result(big, 3, 200)
+        assert ei.value.status == capi.CCM_E_NOTFOUND
+        jobs = make_jobs(3, seed=11)
+        tickets = [srv.submit(j["X"], j["Y"], j["E"], j["tau"], j["L"], j["r"], j["seed"])
+                   for j in jobs]
+        out = []
+        for t, j in zip(tickets, jobs):
+            assert srv.wait(t) == capi.CCM_OK
+            out.append(srv.result(t, len(j["L"]), j["r"]))
+    for (rxy, ryx, _), j in zip(out, jobs):
+        axy, ayx, _ = run_alone(ctx, j)
+        assert np.array_equal(rxy, axy, equal_nan=True)
+        assert np.array_equal(ryx, ayx, equal_nan=True)
+
+
+def test_server_job_stream_vs_oracle(ctx, orc):
+    """The first six jobs of the bench's job stream (N up to 5*10^4, every
+    tau, r = 100) served together: each equals the job alone bit for bit,
+    and three realizations per job (a small, a middle and the full library,
+    directions alternating) equal the oracle."""
+    stream = synth.job_stream(6, 1.0, seed=4)
+    series = [j["make"]() for j in stream]
+    with capi.Server(ctx) as srv:
+        tickets = [srv.submit(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"])
+                   for (X, Y), j in zip(series, stream)]
+        out = []
+        for t, j in zip(tickets, stream):
+            assert srv.wait(t) == capi.CCM_OK
+            out.append(srv.result(t, len(j["L"]), j["r"]))
+    for k, ((rxy, ryx, _), (X, Y), j) in enumerate(zip(out, series, stream)):
+        axy, ayx, _ = ctx.ccm(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"])
+        assert np.array_equal(rxy, axy, equal_nan=True)
+        assert np.array_equal(ryx, ayx, equal_nan=True)
+        for n, il in enumerate((2, 6, len(j["L"]) - 1)):
+            ri = (7 * k + 31 * n) % j["r"]
+            d = (k + n) % 2
+            S, T = (Y, X) if d == 0 else (X, Y)
+            want = orc.realization_split(S, T, j["E"], j["tau"], j["L"][il], ri, j["seed"])
+            got = (rxy if d == 0 else ryx)[il, ri]
+            assert abs(got - want) < 1e-5, (k, il, ri, d, got, want)

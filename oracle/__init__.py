@@ -234,6 +234,27 @@ class Oracle:
         return int(self.lib.oracle_ccm(_ptr(X), _ptr(Y), N, E, tau, _ptr(Ls), nL, r, 1,
                                        excl, 0, _ptr(rxy), _ptr(ryx), _ptr(le)))
 
+    def realization_split(self, S, T, E, tau, L, r_index, seed, excl=0, threads=None,
+                          chunk=2048):
+        """rho of one realization (every embedded point a query) with its queries
+        split over threads: the library from ``sample_library``, each chunk's
+        predictions from ``neighbors_at``, then the skill from ``pearson`` of
+        the observed and predicted values -- the steps ``realization`` takes,
+        in its query order, so the result is the same (pinned)."""
+        S, T = _f64(S), _f64(T)
+        N = len(S)
+        off = (E - 1) * tau
+        Ne = N - off
+        le = min(int(L), Ne)
+        lib = self.sample_library(seed, E, tau, le, r_index, Ne)
+        qs = np.arange(Ne, dtype=np.int64)
+        parts = [qs[a:a + chunk] for a in range(0, Ne, chunk)]
+        threads = threads or default_threads()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            preds = list(ex.map(lambda q: self.neighbors_at(S, T, E, tau, lib, q, excl)[2],
+                                parts))
+        return self.pearson(T[off:off + Ne], np.concatenate(preds))
+
     def realizations_threaded(self, tasks, threads=None):
         """rho of many realizations; ``tasks`` holds ``realization`` argument tuples."""
         threads = threads or default_threads()

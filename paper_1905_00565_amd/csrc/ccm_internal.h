@@ -152,7 +152,8 @@ struct Moments {
   double n, mt, mp, m2t, m2p, c;
 };
 
-// Optional per-query dump (test hook), rows indexed by embedded point.
+// Optional per-query dump (test hook), rows indexed by embedded point;
+// nbr == nullptr means none.
 struct Dump {
   int32_t* nbr;   // [n_e][E+1]
   float* d2;      // [n_e][E+1]
@@ -160,7 +161,9 @@ struct Dump {
 };
 
 // Launchers (defined with the kernels).
-int crossmap_queries_per_lane(int E, bool dump);
+// Queries per lane of the cross-map kernel of E (a tile holds kBlock times
+// as many); the same for batched launches and the per-query hook.
+int crossmap_queries_per_lane(int E);
 // E-sweep sharing: queries per lane of the scan at E_max (its key registers
 // grow as E_max^2, so this falls with E_max).
 int shared_queries_per_lane(int emax);
@@ -180,7 +183,9 @@ hipError_t launch_gather(const GatherJob* jobs, int64_t n_jobs, int64_t max_n_e,
                          const float* emb, const int32_t* lib, const int32_t* order,
                          float* pts, int32_t* pj, int32_t* start, hipStream_t st);
 hipError_t launch_zero_int(int* p, int n, hipStream_t st);
-hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
+// d.nbr == nullptr: no per-query export; else (the hook) d.nbr, d.d2 and
+// d.pred are all set and the kernel instance that exports them runs.
+hipError_t launch_crossmap(int E, int mode, int grid,
                            const Realization* rzs, const Item* items,
                            int n_items, int* next, const float* emb,
                            const float* pts, const int32_t* pj,

@@ -810,6 +810,10 @@ __device__ __forceinline__ void simplex_weights(const float (&nd)[K], double (&w
   for (int t = 0; t < K; ++t) w[t] = u[t] / su;
 }
 
+// DUMP (the test hook): every query's neighbours, squared distances and
+// prediction are written out as well.  The hook's instance has the batched
+// launches' Q, candidate groups, tiles and merge order; only the export
+// after the scan differs.
 template <int E, int Q, int MODE, bool DUMP, bool TBL>
 __device__ __forceinline__ void crossmap_item(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
@@ -1642,20 +1646,13 @@ using CrossmapFn = void (*)(const Realization*, const Item*, int, int*,
                             const int32_t*, const int32_t*, const double*,
                             Moments*, int, int, Dump, TableArgs);
 
-template <int E, int Q, bool TBL>
+template <int E, int Q, bool DUMP, bool TBL>
 struct QSetT {
-  static CrossmapFn get(int mode, bool dump) {
-    if (dump) {
-      switch (mode) {
-        case kExclSelf: return k_crossmap<E, 1, kExclSelf, true, TBL>;
-        case kKeepSelf: return k_crossmap<E, 1, kKeepSelf, true, TBL>;
-        default: return k_crossmap<E, 1, kWindow, true, TBL>;
-      }
-    }
+  static CrossmapFn get(int mode) {
     switch (mode) {
-      case kExclSelf: return k_crossmap<E, Q, kExclSelf, false, TBL>;
-      case kKeepSelf: return k_crossmap<E, Q, kKeepSelf, false, TBL>;
-      default: return k_crossmap<E, Q, kWindow, false, TBL>;
+      case kExclSelf: return k_crossmap<E, Q, kExclSelf, DUMP, TBL>;
+      case kKeepSelf: return k_crossmap<E, Q, kKeepSelf, DUMP, TBL>;
+      default: return k_crossmap<E, Q, kWindow, DUMP, TBL>;
     }
   }
 };
@@ -1663,7 +1660,8 @@ struct QSetT {
 template <int E, int Q>
 struct QSet {
   static CrossmapFn get(int mode, bool dump, bool tbl) {
-    return tbl ? QSetT<E, Q, true>::get(mode, dump) : QSetT<E, Q, false>::get(mode, dump);
+    if (dump) return tbl ? QSetT<E, Q, true, true>::get(mode) : QSetT<E, Q, true, false>::get(mode);
+    return tbl ? QSetT<E, Q, false, true>::get(mode) : QSetT<E, Q, false, false>::get(mode);
   }
 };
 
@@ -1680,7 +1678,7 @@ static CrossmapFn crossmap_kernel(int E, int mode, bool dump, bool tbl, int* q_o
   switch (E) {
 #define CCM_CASE(e)                                           \
   case e:                                                     \
-    q = dump ? 1 : DefaultQ<e>::Q;                            \
+    q = DefaultQ<e>::Q;                                       \
     f = QSet<e, DefaultQ<e>::Q>::get(mode, dump, tbl);        \
     break;
     CCM_CASE(1) CCM_CASE(2) CCM_CASE(3) CCM_CASE(4) CCM_CASE(5)
@@ -1714,9 +1712,9 @@ int shared_queries_per_lane(int emax) {
   return emax >= 1 && emax <= kMaxE ? kSharedQ[emax] : 0;
 }
 
-int crossmap_queries_per_lane(int E, bool dump) {
+int crossmap_queries_per_lane(int E) {
   int q = 0;
-  crossmap_kernel(E, kExclSelf, dump, false, &q);
+  crossmap_kernel(E, kExclSelf, false, false, &q);
   return q;
 }
 
@@ -1900,7 +1898,7 @@ hipError_t launch_crossmap_shared(int emax, int mode, int grid, const Realizatio
   }
 }
 
-hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
+hipError_t launch_crossmap(int E, int mode, int grid,
                            const Realization* rzs, const Item* items,
                            int n_items, int* next, const float* emb,
                            const float* pts, const int32_t* pj,
@@ -1909,7 +1907,7 @@ hipError_t launch_crossmap(int E, int mode, bool dump, int grid,
                            int window, Dump d, const int32_t* table, int table_n_e,
                            hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  CrossmapFn f = crossmap_kernel(E, mode, dump, table_n_e > 0, nullptr);
+  CrossmapFn f = crossmap_kernel(E, mode, d.nbr != nullptr, table_n_e > 0, nullptr);
   if (!f) return hipErrorInvalidValue;
   const TableArgs ta{table, table_lds_words(table_n_e), 0};
   hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), table_lds_bytes(E, table_n_e), st,

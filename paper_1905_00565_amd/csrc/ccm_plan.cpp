@@ -119,7 +119,7 @@ static Plan make_plan_nested(const Spec& s) {
   p.L_eff.assign((size_t)nE * nT * nL, 0);
   for (int ie = 0; ie < nE; ++ie) {
     const int32_t E = s.E[ie];
-    const int Q = crossmap_queries_per_lane(E, false);
+    const int Q = crossmap_queries_per_lane(E);
     const int64_t qt = (int64_t)kBlock * Q;
     for (int it = 0; it < nT; ++it) {
       const int32_t tau = s.tau[it];
@@ -393,7 +393,7 @@ Plan make_plan(const Spec& s) {
 
   for (int ie = 0; ie < nE; ++ie) {
     const int32_t E = s.E[ie];
-    const int Q = crossmap_queries_per_lane(E, false);
+    const int Q = crossmap_queries_per_lane(E);
     const int64_t qt = (int64_t)kBlock * Q;
     for (int it = 0; it < nT; ++it) {
       const int32_t tau = s.tau[it];
@@ -523,7 +523,7 @@ Plan make_plan_matrix(const Spec& s) {
   p.ingest.push_back({0, 0, (int64_t)M * N});
   p.n_out = (int64_t)M * M * nL * s.r;
   p.L_eff.assign(nL, 0);
-  const int Q = crossmap_queries_per_lane(E, false);
+  const int Q = crossmap_queries_per_lane(E);
   const int64_t qt = (int64_t)kBlock * Q;
   const int32_t sorted = ne <= gather_max_sorted_n_e() ? 1 : 0;
   if (sorted) p.max_sorted_n_e = ne;

@@ -197,7 +197,7 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                      p.spec.M, ex->d_partial.p, p.spec.query_set,
                                      p.window, table, p.e_table_ne[E], st));
       else
-        HIPCHK(launch_crossmap(E, p.mode, false, grid, ex->d_rz.as<Realization>(),
+        HIPCHK(launch_crossmap(E, p.mode, grid, ex->d_rz.as<Realization>(),
                                ex->d_items.as<Item>() + p.e_first[E], n, next,
                                ex->d_emb.as<float>(), ex->d_pts.as<float>(),
                                ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
@@ -241,7 +241,7 @@ void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
                                      ex->d_partial.p, p.spec.query_set, p.window, table,
                                      R.table_off >= 0 ? R.n_e : 0, st));
       else
-        HIPCHK(launch_crossmap(R.E, p.mode, false, R.n_tiles, ex->d_rz.as<Realization>(),
+        HIPCHK(launch_crossmap(R.E, p.mode, R.n_tiles, ex->d_rz.as<Realization>(),
                                ex->d_plain_items.as<Item>() + ex->plain_first[r],
                                R.n_tiles, nullptr, ex->d_emb.as<float>(),
                                ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
@@ -534,7 +534,7 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
       if (lib_idx[i] < 0 || lib_idx[i] >= ne) fail(CCM_E_INVAL, "lib_idx out of range");
       if (i > 0 && lib_idx[i] <= lib_idx[i - 1]) fail(CCM_E_INVAL, "lib_idx not ascending");
     }
-    const int Q = crossmap_queries_per_lane(E, true);
+    const int Q = crossmap_queries_per_lane(E);
     const int64_t nq = qs ? L_eff : ne;
     const int64_t qt = (int64_t)kBlock * Q;
     const int n_tiles = (int)((nq + qt - 1) / qt);
@@ -644,7 +644,7 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
       HIPCHK(launch_table_build(E, d_tj.as<TableJob>(), 1, (int)ne, d_emb.as<float>(),
                                 d_tab.as<int32_t>(), st));
     Dump dump{d_nbr.as<int32_t>(), d_d2.as<float>(), d_pred.as<double>()};
-    HIPCHK(launch_crossmap(E, excl_mode(excl), true, n_tiles, d_rz.as<Realization>(),
+    HIPCHK(launch_crossmap(E, excl_mode(excl), n_tiles, d_rz.as<Realization>(),
                            d_items.as<Item>(), n_tiles, nullptr, d_emb.as<float>(),
                            d_pts.as<float>(), d_pj.as<int32_t>(), d_qord.as<int32_t>(),
                            d_start.as<int32_t>(), d_s64.as<double>(),

@@ -330,6 +330,45 @@ def _py_nested(seed, E, tau, r_index, Ne, n):
     return out
 
 
+def _py_selection(seed, E, tau, L_eff, r_index, Ne):
+    """Selection sampling restated with Python integers from Knuth's Algorithm
+    S (TAOCP Vol. 2, Sec. 3.4.2): with t candidates seen and m chosen, take
+    candidate t when a uniform integer below Ne - t falls below L_eff - m; the
+    uniform integer is the high word of one 64-bit draw times (Ne - t).  The
+    draws come from the SplitMix64 stream whose state is the key folded one
+    field at a time, in the order (seed, E, tau, L_eff, r_index)."""
+    st = 0
+    for v in (seed, E, tau, L_eff, r_index):
+        st = _py_splitmix_mix(st ^ (v & MASK64))
+    chosen = []
+    for t in range(Ne):
+        if len(chosen) == L_eff:
+            break
+        st = (st + 0x9E3779B97F4A7C15) & MASK64
+        u = (_py_splitmix_mix(st) * (Ne - t)) >> 64
+        if u < L_eff - len(chosen):
+            chosen.append(t)
+    return chosen
+
+
+def pin_sampler_python(orc):
+    """The library draw equals an independent statement of the stream and of
+    Algorithm S, on a grid of keys: seeds near 0 and near 2^64, every E, taus,
+    sizes from 1 to the whole set, the sweep's and long series' sizes."""
+    keys = [(1, 2, 1, 100, 0, 999), (2, 10, 5, 348, 249, 9955), (3, 3, 2, 1000, 17, 2500),
+            (2**64 - 1, 1, 1, 1, 3, 40), (12345678901234567, 7, 3, 499, 1, 500),
+            (0, 4, 1, 20, 99, 1997), (5, 6, 4, 137, 7, 1480), (2, 1, 1, 2976, 3, 10000)]
+    for E in range(1, 11):
+        keys.append((2, E, 1 + E % 5, 100 + 37 * E, E * 25, 10000 - (E - 1) * (1 + E % 5)))
+    for seed, E, tau, le, ri, ne in keys:
+        got = orc.sample_library(seed, E, tau, le, ri, ne).tolist()
+        assert got == _py_selection(seed, E, tau, le, ri, ne), (seed, E, tau, le, ri, ne)
+    st = 0
+    for v in (9, 3, 2, 50, 4):
+        st = _py_splitmix_mix(st ^ v)
+    assert orc.library_state(9, 3, 2, 50, 4) == st
+
+
 def pin_nested_structure(orc):
     """Nested ordering: distinct points in range, a permutation when complete,
     shorter draws are prefixes of longer ones, every key field matters, and
@@ -474,6 +513,7 @@ ALL_PINS = [
     pin_splitmix64_known_answers,
     pin_sampler_structure,
     pin_sampler_uniform,
+    pin_sampler_python,
     pin_nested_structure,
     pin_nested_uniform,
     pin_nested_ccm,

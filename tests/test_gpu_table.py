@@ -1,12 +1,14 @@
-"""Distance indexing table (CCM_FLAG_TABLE, Section 3.2) against the scan.
+"""Distance indexing table (CCM_FLAG_TABLE, Section 3.2) against the oracle
+and against the scan.
 
 Walking a query's table row to its first E+1 library members selects exactly
-the neighbours the brute-force scan selects, so neighbours, squared
-distances, predictions and rho must agree bit for bit with the flag off (the
-brute-force side is pinned to the oracle in test_gpu_parity).  The cases
-cover rows shorter than the series (walks that run short and fall back to
-the scan), full rows, ties and zero distances, every exclusion mode, library
-queries, every form of the batched call and the causal matrix.
+the neighbours the brute-force definition selects, so neighbours and squared
+distances must equal the CPU oracle's bit for bit (predictions and rho
+within 1e-5), and every output must agree bit for bit with the flag off.
+The cases cover rows shorter than the series (walks that run short and fall
+back to the scan), full rows, ties and zero distances, every exclusion mode,
+library queries, every form of the batched call, the causal matrix and the
+bench's full sweep (sampled realizations against the oracle).
 """
 import zlib
 
@@ -17,6 +19,17 @@ from paper_1905_00565_amd import capi, synth
 
 pytestmark = pytest.mark.gpu
 TABLE = capi.CCM_FLAG_TABLE
+TOL = 1e-5
+
+
+def close(a, b, tol=TOL):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    assert a.shape == b.shape
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    m = ~np.isnan(a)
+    if m.any():
+        err = np.max(np.abs(a[m] - b[m]))
+        assert err < tol, err
 
 
 @pytest.fixture(scope="module")
@@ -56,11 +69,16 @@ NEIGHBOR_CASES = [
     (2000, 3, 1, 1200, 4, 0, "logistic"),     # exclusion window
     (2000, 5, 1, 1500, 0, 1, "gauss"),        # library points as queries
     (1200, 1, 1, 900, 0, 0, "quantised"),
+    # rows of 1024 against N_e / L_eff far above E + 1: most walks run short
+    (6000, 2, 1, 30, 0, 0, "logistic"),
+    (5000, 7, 3, 200, 0, 0, "logistic"),
+    (4000, 3, 1, 40, 3, 0, "logistic"),       # short rows and an exclusion window
+    (4000, 4, 1, 120, -1, 1, "quantised"),    # short rows, query kept, library queries
 ]
 
 
 @pytest.mark.parametrize("case", NEIGHBOR_CASES, ids=[str(c) for c in NEIGHBOR_CASES])
-def test_table_neighbors_bitwise(ctx, case):
+def test_table_neighbors_bitwise(ctx, orc, case):
     N, E, tau, L, excl, qs, kind = case
     rng = np.random.default_rng(zlib.crc32(repr(case).encode()))
     S, T = series(kind, N, rng)
@@ -68,6 +86,13 @@ def test_table_neighbors_bitwise(ctx, case):
     lib = np.sort(rng.choice(ne, size=min(L, ne), replace=False)).astype(np.int32)
     a = ctx.ccm_neighbors(S, T, E, tau, lib, exclusion_radius=excl, query_set=qs)
     b = ctx.ccm_neighbors(S, T, E, tau, lib, exclusion_radius=excl, query_set=qs, flags=TABLE)
+    # the table walk against the brute-force definition
+    o = orc.neighbors(S, T, E, tau, lib, excl=excl, query_set=qs)
+    assert np.array_equal(b[0], o[0]), "table neighbours differ from the oracle"
+    assert bitwise_equal(b[1], o[1]), "table squared distances differ from the oracle"
+    close(b[2], o[2])
+    close(b[3], o[3])
+    # and against the scan, bit for bit
     assert np.array_equal(a[0], b[0])
     assert bitwise_equal(a[1], b[1])
     assert bitwise_equal(a[2], b[2])
@@ -86,7 +111,7 @@ def sweep(ctx, X, Y, E, tau, L, r, seed, **k):
 @pytest.mark.parametrize("flags,excl,qs", [
     (0, 0, 0), (capi.CCM_FLAG_PERSISTENT, 0, 0), (capi.CCM_FLAG_NO_GRAPH, 0, 0),
     (0, 2, 0), (0, -1, 0), (0, 0, 1)])
-def test_table_sweep_bitwise(ctx, flags, excl, qs):
+def test_table_sweep_bitwise(ctx, orc, flags, excl, qs):
     X, Y = synth.coupled_logistic(4000)
     E, tau = [1, 2, 3, 5, 8], [1, 3]
     L = synth.geometric_grid(50, 4000, 8)
@@ -97,6 +122,17 @@ def test_table_sweep_bitwise(ctx, flags, excl, qs):
     assert pa["table_realizations"] == 0
     assert pb["table_realizations"] > 0.3 * pb["realizations"]
     assert bitwise_equal(a, b)
+    # realizations with the largest libraries (the ones that walk a table)
+    # against the oracle, every (E, tau), alternating directions and r
+    picks, tasks = [], []
+    for ie, e in enumerate(E):
+        for it, t in enumerate(tau):
+            for il in (len(L) - 3, len(L) - 1):
+                d, ri = (ie + it + il) % 2, (3 * ie + it + il) % 6
+                S, T = (Y, X) if d == 0 else (X, Y)
+                picks.append((d, ie, it, il, ri))
+                tasks.append((S, T, e, t, L[il], ri, 11, excl, qs))
+    close([b[p] for p in picks], orc.realizations_threaded(tasks))
 
 
 def test_table_plain_form(ctx):
@@ -109,7 +145,7 @@ def test_table_plain_form(ctx):
         assert bitwise_equal(u, v) and bitwise_equal(u, w)
 
 
-def test_table_matrix(ctx):
+def test_table_matrix(ctx, orc):
     S, _ = synth.logistic_network(6, 3000, seed=5)
     L = [150, 1200, 3000]
     ctx.profile_enable(True)
@@ -120,9 +156,12 @@ def test_table_matrix(ctx):
     ctx.profile_enable(False)
     assert p["table_realizations"] > 0
     assert bitwise_equal(a, b)
+    picks = [(0, 1, 2, 0), (3, 5, 1, 2), (5, 2, 2, 1), (4, 0, 1, 1)]
+    tasks = [(S[i], S[j], 3, 1, L[il], ri, 9, 0, 0) for i, j, il, ri in picks]
+    close([b[p] for p in picks], orc.realizations_threaded(tasks))
 
 
-def test_table_long_series_sample(ctx):
+def test_table_long_series_sample(ctx, orc):
     """Rows truncated far below the series length (N = 10^5)."""
     w = synth.workload_long(r=2)
     L = [1000, 50000, 100000]
@@ -130,13 +169,37 @@ def test_table_long_series_sample(ctx):
     b = ctx.ccm(w.X, w.Y, 3, 2, L, 2, w.seed, flags=TABLE)
     for u, v in zip(a[:2], b[:2]):
         assert bitwise_equal(u, v)
+    # the walked realizations (large libraries) against the oracle
+    tasks = [(w.Y, w.X, 3, 2, 50000, 1, w.seed, 0, 0), (w.X, w.Y, 3, 2, 100000, 0, w.seed, 0, 0)]
+    close([b[0][1, 1], b[1][2, 0]], orc.realizations_threaded(tasks))
+    # sampled queries of the table hook on the long series against the oracle
+    ne = len(w.X) - 2 * 2
+    lib = ctx.ccm_library(ne, 3, 2, 50000, 1, w.seed)
+    nbr, d2, pred, _ = ctx.ccm_neighbors(w.Y, w.X, 3, 2, lib, flags=TABLE)
+    q = np.random.default_rng(8).choice(ne, 256, replace=False)
+    on, od, op = orc.neighbors_at(w.Y, w.X, 3, 2, lib, q)
+    assert np.array_equal(nbr[q], on) and bitwise_equal(d2[q], od)
+    close(pred[q], op)
 
 
-def test_table_full_sweep_bitwise(ctx):
+def test_table_full_sweep_bitwise(ctx, orc):
     """The bench's sweep in full (N = 10^4, E = 1..10, tau = 1..5, 20 L,
-    r = 250) through the tables equals the brute-force sweep bit for bit."""
+    r = 250) through the tables equals the brute-force sweep bit for bit,
+    and sampled walked realizations (the 8 largest L of every E) equal the
+    oracle."""
     w = synth.workload_sweep()
     a, pa = sweep(ctx, w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed)
     b, pb = sweep(ctx, w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed, flags=TABLE)
     assert pb["table_realizations"] > 0.5 * pb["realizations"]
     assert bitwise_equal(a, b)
+    rng = np.random.default_rng(31)
+    picks, tasks = [], []
+    for ie, e in enumerate(w.E):
+        for k in range(2):
+            it = int(rng.integers(len(w.tau)))
+            il = int(rng.integers(len(w.L) - 8, len(w.L) - 1))
+            ri, d = int(rng.integers(w.r)), (ie + k) % 2
+            S, T = (w.Y, w.X) if d == 0 else (w.X, w.Y)
+            picks.append((d, ie, it, il, ri))
+            tasks.append((S, T, e, w.tau[it], w.L[il], ri, w.seed, 0, 0))
+    close([b[p] for p in picks], orc.realizations_threaded(tasks))

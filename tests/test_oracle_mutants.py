@@ -51,6 +51,13 @@ MUTANTS = [
     ("nested library is a suffix", "st = oracle_neighbors(Y, X, N, E, tau, perm, le,",
      "st = oracle_neighbors(Y, X, N, E, tau, perm + (Lmax - le), le,"),
     ("splitmix constant", "0xbf58476d1ce4e5b9ULL", "0xbf58476d1ce4e5b8ULL"),
+    ("sampler key folds tau before E",
+     "    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)E);\n    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)tau);\n    s = oracle_sm64_mix(s ^ (uint64_t)L_eff);",
+     "    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)tau);\n    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)E);\n    s = oracle_sm64_mix(s ^ (uint64_t)L_eff);"),
+    ("sampler key folds r twice",
+     "    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)r_index);\n    return s;\n}\n\n/*\n * Selection",
+     "    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)r_index);\n    s = oracle_sm64_mix(s ^ (uint64_t)(int64_t)r_index);\n    return s;\n}\n\n/*\n * Selection"),
+    ("sampler draw without the gamma step", "    *state += 0x9e3779b97f4a7c15ULL;\n", "    *state ^= 0x9e3779b97f4a7c15ULL;\n"),
     ("clamp one short", "const int64_t Le = L < Ne ? L : Ne;",
      "const int64_t Le = L < Ne ? L : Ne - 1;"),
     ("query set ignored", "const int64_t i = query_set ? lib[q] : q;", "const int64_t i = q;"),

@@ -140,6 +140,22 @@ void ccm_destroy(ccm_ctx *ctx);
 const char *ccm_last_error(const ccm_ctx *ctx);
 
 /*
+ * Memory bound of the batched calls (ccm, ccm_sweep, ccm_matrix and their
+ * device forms).  Each realization needs its drawn library (the paper's
+ * subsample, Section 3.1) and that library laid out for the scan: about
+ * L_eff * (E + 2) * 4 bytes of device memory (nested libraries: also N_e * 4
+ * per ordering).  The realizations of a call run in waves whose libraries
+ * together fit `bytes`: all realizations of one E in one wave when they
+ * fit, consecutive E merged while they fit, one E split over several waves
+ * when it alone does not fit (at least one realization per wave).  The
+ * results do not depend on the bound; other buffers of a call (series,
+ * embeddings, visiting orders, per-tile moments) are not counted.  bytes = 0
+ * restores the default, min(8 GiB, device memory / 8) and at least 1 GiB.
+ * The bound applies to calls made after it is set.
+ */
+ccm_status ccm_set_wave_limit(ccm_ctx *ctx, uint64_t bytes);
+
+/*
  * Cross map in both directions for one (E, tau): Introduction and
  * Sections 2.1, 3.1, 3.2.
  *   X, Y        host double[N] series
@@ -327,6 +343,7 @@ typedef struct {
   double predictions;    /* cross-map predictions made */
   double realizations;   /* rho values produced */
   double table_realizations; /* of which walked a distance indexing table */
+  double waves;          /* waves of realizations run (ccm_set_wave_limit) */
 } ccm_profile;
 
 ccm_status ccm_profile_enable(ccm_ctx *ctx, int on);

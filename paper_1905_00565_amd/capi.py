@@ -37,7 +37,7 @@ CCM_TABLE_WIDTH = 1024
 
 # Every symbol include/ccm.h declares (checked by the ABI test).
 EXPORTS = [
-    "ccm_create", "ccm_destroy", "ccm_last_error", "ccm", "ccm_sweep",
+    "ccm_create", "ccm_destroy", "ccm_last_error", "ccm_set_wave_limit", "ccm", "ccm_sweep",
     "ccm_matrix", "ccm_dev", "ccm_sweep_dev", "ccm_matrix_dev", "ccm_library",
     "ccm_nested_library", "ccm_neighbors",
     "ccm_profile_enable", "ccm_profile_read",
@@ -55,7 +55,7 @@ class ccm_profile(C.Structure):
     _fields_ = [("kernel_ms", C.c_double), ("launches", C.c_int64),
                 ("pairs", C.c_double), ("flops", C.c_double),
                 ("predictions", C.c_double), ("realizations", C.c_double),
-                ("table_realizations", C.c_double)]
+                ("table_realizations", C.c_double), ("waves", C.c_double)]
 
 
 class ccm_server_cfg(C.Structure):
@@ -104,6 +104,7 @@ def lib():
         L.ccm_destroy.restype = None
         L.ccm_last_error.argtypes = [P]
         L.ccm_last_error.restype = C.c_char_p
+        L.ccm_set_wave_limit.argtypes = [P, u64]
         L.ccm.argtypes = [P, P, P, i64, i32, i32, P, i32, i32, u64, P, P, P, P]
         L.ccm_sweep.argtypes = [P, P, P, i64, P, i32, P, i32, P, i32, i32, u64, P, P]
         L.ccm_dev.argtypes = [P, P, P, i64, i32, i32, P, i32, i32, u64, P, P, P, P, P]
@@ -180,6 +181,11 @@ def ccm_destroy(ctx) -> None:
 
 def ccm_last_error(ctx) -> str:
     return lib().ccm_last_error(ctx).decode()
+
+
+def ccm_set_wave_limit(ctx, nbytes: int) -> None:
+    """Device bytes of libraries held at once by a batched call (0: default)."""
+    _check(ctx, lib().ccm_set_wave_limit(ctx, int(nbytes)))
 
 
 def ccm(ctx, X, Y, E, tau, L, r, seed, exclusion_radius=0, query_set=0, flags=0):
@@ -410,6 +416,9 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_wave_limit(self, nbytes):
+        ccm_set_wave_limit(self.handle, nbytes)
 
     def ccm(self, *a, **k):
         return ccm(self.handle, *a, **k)

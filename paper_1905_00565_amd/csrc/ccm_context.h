@@ -12,6 +12,44 @@ struct EvPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
+// Device addresses of one plan's buffers: an Exec's own allocations, or
+// ranges of the static workspace of the no-allocation entry point.
+struct PlanBuffers {
+  IngestJob* ingest = nullptr;
+  EmbedJob* embed = nullptr;
+  SampleJob* sample = nullptr;
+  GatherJob* gather = nullptr;
+  Realization* rz = nullptr;
+  Item* items = nullptr;
+  Item* plain_items = nullptr;       // CCM_FLAG_PLAIN: each realization's items
+  OrderJob* orders = nullptr;
+  int32_t* segoff = nullptr;
+  double* s64 = nullptr;
+  float* s32 = nullptr;
+  int32_t* iota = nullptr;
+  uint32_t* keys = nullptr;
+  uint32_t* keys_out = nullptr;
+  int32_t* order = nullptr;
+  void* sort_temp = nullptr;
+  int32_t* qord = nullptr;
+  int32_t* start = nullptr;
+  float* emb = nullptr;
+  int32_t* lib = nullptr;
+  float* pts = nullptr;
+  int32_t* pj = nullptr;
+  void* partial = nullptr;
+  double* out = nullptr;
+  int* counter = nullptr;            // one per launch (persistent grids)
+  int32_t* self = nullptr;           // causal matrix
+  double* tt = nullptr;
+  TableJob* tables = nullptr;        // distance indexing tables
+  int32_t* table = nullptr;
+  NestedJob* nested = nullptr;       // nested libraries
+  int32_t* shuffle = nullptr;
+  int32_t* segs = nullptr;
+  Realization* rz_fin = nullptr;
+};
+
 struct Exec {
   Plan plan;
   DevBuf d_ingest, d_embed, d_sample, d_gather, d_rz, d_items, d_plain_items;
@@ -22,6 +60,7 @@ struct Exec {
   DevBuf d_tables, d_table;   // distance indexing table jobs and rows
   DevBuf d_nested, d_scratch, d_segs, d_rz_fin;   // nested libraries
   std::vector<int64_t> plain_first;   // per realization: first plain item
+  PlanBuffers buf;
   hipGraphExec_t graph = nullptr;
   ~Exec() {
     if (graph) (void)hipGraphExecDestroy(graph);
@@ -33,6 +72,7 @@ struct Exec {
 struct ccm_ctx {
   int device = 0;
   int num_cus = 0;
+  uint64_t wave_limit = 0;    // see ccm_set_wave_limit
   hipStream_t stream = nullptr;
   std::mutex mu;
   std::string err;
@@ -43,6 +83,12 @@ struct ccm_ctx {
 };
 
 namespace ccmh {
+
+// Queue every launch of plan p on stream st (buffers b; plain_first: each
+// realization's first item in b.plain_items, for CCM_FLAG_PLAIN).  With
+// `timed`, each cross-map launch is bracketed by HIP events of the context.
+void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
+                  const std::vector<int64_t>& plain_first, hipStream_t st, bool timed);
 
 // Run f under the context's lock with HIP errors and exceptions turned into
 // status codes (no exception crosses the C ABI).

@@ -87,11 +87,15 @@ struct Spec {
   int32_t excl = 0;
   int32_t query_set = 0;
   uint32_t flags = 0;
+  // Largest device bytes of drawn libraries and gathered library points held
+  // at once; the realizations are run in waves that fit (0: one wave).
+  uint64_t wave_limit = 0;
 
   bool operator==(const Spec& o) const {
     return M == o.M && N == o.N && E == o.E && tau == o.tau && L == o.L && r == o.r &&
            seed == o.seed && excl == o.excl && query_set == o.query_set &&
-           (flags & ~CCM_FLAG_NO_GRAPH) == (o.flags & ~CCM_FLAG_NO_GRAPH);
+           (flags & ~CCM_FLAG_NO_GRAPH) == (o.flags & ~CCM_FLAG_NO_GRAPH) &&
+           wave_limit == o.wave_limit;
   }
 };
 
@@ -105,6 +109,26 @@ inline int64_t min_library(int32_t E, int32_t excl) {
   const int64_t w = excl < 0 ? 0 : 2 * (int64_t)excl + 1;
   return (int64_t)E + 1 + w;
 }
+
+// One cross-map launch: the work items of one E within a wave.
+struct Launch {
+  int32_t E;
+  int32_t first;      // into Plan::items
+  int32_t count;
+};
+
+// A wave: realizations whose drawn libraries and gathered points are live at
+// once.  Its sample (or nested shuffle) jobs and gather jobs are contiguous
+// ranges, its launches a contiguous range of Plan::launches; the library,
+// gathered-point and shuffle pools are reused by every wave (the plan's
+// n_lib, n_pts, n_pj and n_scratch are the largest wave's).
+struct Wave {
+  int64_t sample_first = 0, sample_count = 0;   // into sample, or nested
+  int64_t gather_first = 0, gather_count = 0;
+  int64_t max_sorted_n_e = 0;                   // largest n_e of its sorted gathers
+  int32_t launch_first = 0, launch_count = 0;
+  uint64_t pool_bytes = 0;
+};
 
 struct Plan {
   Spec spec;
@@ -128,12 +152,17 @@ struct Plan {
   int64_t max_sorted_n_e = 0;
   std::vector<Realization> rz;
   std::vector<int32_t> self_of;       // matrix: searched series of each realization
-  // realization r owns sample job rz_sample[r] and gather job r
+  // realization r uses sample job (or nested shuffle) rz_sample[r] and the
+  // gather jobs from rz_gather[r] on (one, or one per segment of a chain)
   std::vector<int64_t> rz_sample;
-  // batched items grouped by E, longest library first within a group
+  std::vector<int64_t> rz_gather;
+  // waves of realizations (split_waves), and the batched items grouped by
+  // wave, then E, longest library first within a group
+  std::vector<Wave> waves;
+  std::vector<Launch> launches;
+  std::vector<int32_t> wave_rz;       // realizations in wave order
+  std::vector<int64_t> wave_rz_first; // per wave, into wave_rz (+1 sentinel)
   std::vector<Item> items;
-  int e_first[kMaxE + 1] = {0};
-  int e_count[kMaxE + 1] = {0};
   int64_t n_slots = 0;
   int64_t n_out = 0;
   std::vector<int64_t> L_eff;   // per (iE, itau, iL)
@@ -187,6 +216,9 @@ Plan make_plan(const Spec& s);
 // Causal matrix: M series, one (E, tau); libraries per (L, r) shared by every
 // series; one realization per (searched series, L, r) predicting all others.
 Plan make_plan_matrix(const Spec& s);
+
+// Default wave limit of a device with `total` bytes of memory.
+uint64_t default_wave_limit(uint64_t total);
 
 // Host series: finite and |value| <= 1e17 (keeps binary32 d2 finite).
 void check_host_series(const double* s, int64_t n, const char* name);

@@ -1,5 +1,8 @@
 // ccm_plan.cpp -- validation of a call and layout of its realizations,
 // work items and device pools (the planner of libccm).
+#include <numeric>
+#include <unordered_map>
+
 #include "ccm_host.h"
 
 namespace ccmh {
@@ -73,27 +76,190 @@ int64_t table_for(Plan& p, int64_t emb_off, int64_t ne, int E) {
   return t.out_off;
 }
 
-// Items grouped by E, the costliest first within a group: a scan costs
-// n_query * l_eff pairs, a table walk about n_query * (E+1) n_e / l_eff
-// row entries.
+uint64_t default_wave_limit(uint64_t total) {
+  return std::max<uint64_t>(1ull << 30, std::min<uint64_t>(8ull << 30, total / 8));
+}
+
+// Pool bytes of one realization in its wave: its gathered library (binary32
+// coordinates and int32 indices), and, once per wave, its library draw (a
+// nested shuffle also keeps its n_e positions).
+static uint64_t draw_bytes(const Plan& p, int64_t sj) {
+  if (!p.nested.empty()) return ((uint64_t)p.nested[sj].n_out + (uint64_t)p.nested[sj].n_e) * 4;
+  return (uint64_t)p.sample[sj].l_eff * 4;
+}
+static uint64_t points_bytes(const Realization& R) {
+  return (uint64_t)R.l_eff * (uint64_t)(R.E + 1) * 4;
+}
+
+// Group the realizations into waves whose pools fit spec.wave_limit (0: one
+// wave): all realizations of one E together when they fit, consecutive E
+// merged while they fit, an E too large for one wave split into several.
+// Then lay out each wave's draws and gathered libraries from offset 0 of
+// the shared pools (a draw used by realizations of two waves is drawn in
+// both) and rebase the realizations and jobs that refer to them.
+static void split_waves(Plan& p) {
+  const uint64_t limit = p.spec.wave_limit;
+  const bool nested = !p.nested.empty();
+  const size_t n = p.rz.size();
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return p.rz[a].E < p.rz[b].E; });
+
+  std::vector<std::vector<int32_t>> waves;
+  std::vector<int32_t> cur;
+  std::unordered_map<int64_t, int> cur_draws;
+  uint64_t cur_b = 0;
+  auto close_wave = [&] {
+    if (!cur.empty()) waves.push_back(std::move(cur));
+    cur.clear();
+    cur_draws.clear();
+    cur_b = 0;
+  };
+  auto add = [&](int32_t r) {
+    cur.push_back(r);
+    cur_b += points_bytes(p.rz[r]);
+    if (cur_draws.emplace(p.rz_sample[r], 1).second) cur_b += draw_bytes(p, p.rz_sample[r]);
+  };
+  for (size_t g0 = 0; g0 < n;) {
+    size_t g1 = g0;
+    while (g1 < n && p.rz[order[g1]].E == p.rz[order[g0]].E) ++g1;
+    // bytes of the whole E group (its draws counted once each)
+    uint64_t gb = 0;
+    {
+      std::unordered_map<int64_t, int> d;
+      for (size_t k = g0; k < g1; ++k) {
+        gb += points_bytes(p.rz[order[k]]);
+        if (d.emplace(p.rz_sample[order[k]], 1).second) gb += draw_bytes(p, p.rz_sample[order[k]]);
+      }
+    }
+    if (limit == 0 || cur_b + gb <= limit) {
+      for (size_t k = g0; k < g1; ++k) add(order[k]);
+    } else if (gb <= limit) {
+      close_wave();
+      for (size_t k = g0; k < g1; ++k) add(order[k]);
+    } else {
+      close_wave();
+      for (size_t k = g0; k < g1; ++k) {
+        const int32_t r = order[k];
+        uint64_t b = points_bytes(p.rz[r]);
+        if (!cur_draws.count(p.rz_sample[r])) b += draw_bytes(p, p.rz_sample[r]);
+        if (!cur.empty() && cur_b + b > limit) close_wave();
+        add(r);
+      }
+    }
+    g0 = g1;
+  }
+  close_wave();
+
+  std::vector<SampleJob> sample;
+  std::vector<NestedJob> shuffles;
+  std::vector<GatherJob> gather;
+  int64_t max_lib = 0, max_pts = 0, max_pj = 0, max_scr = 0;
+  p.waves.clear();
+  p.wave_rz.clear();
+  p.wave_rz_first.clear();
+  for (const auto& wr : waves) {
+    Wave w;
+    w.sample_first = nested ? (int64_t)shuffles.size() : (int64_t)sample.size();
+    w.gather_first = (int64_t)gather.size();
+    p.wave_rz_first.push_back((int64_t)p.wave_rz.size());
+    std::unordered_map<int64_t, int64_t> remap;   // draw: old index -> new index
+    int64_t lib = 0, pts = 0, pj = 0, scr = 0;
+    for (int32_t r : wr) {
+      p.wave_rz.push_back(r);
+      const int64_t sj = p.rz_sample[r];
+      int64_t old_out = 0, new_out = 0;
+      auto it = remap.find(sj);
+      if (nested) {
+        old_out = p.nested[sj].out_off;
+        if (it == remap.end()) {
+          NestedJob j = p.nested[sj];
+          j.out_off = lib;
+          j.scratch_off = scr;
+          lib += j.n_out;
+          scr += j.n_e;
+          it = remap.emplace(sj, (int64_t)shuffles.size()).first;
+          shuffles.push_back(j);
+        }
+        new_out = shuffles[it->second].out_off;
+      } else {
+        old_out = p.sample[sj].out_off;
+        if (it == remap.end()) {
+          SampleJob j = p.sample[sj];
+          j.out_off = lib;
+          lib += j.l_eff;
+          it = remap.emplace(sj, (int64_t)sample.size()).first;
+          sample.push_back(j);
+        }
+        new_out = sample[it->second].out_off;
+      }
+      Realization& R = p.rz[r];
+      const int64_t ng = nested ? R.n_seg : 1;
+      const int64_t g0 = p.rz_gather[r];
+      p.rz_gather[r] = (int64_t)gather.size();
+      for (int64_t g = g0; g < g0 + ng; ++g) {
+        GatherJob G = p.gather[g];
+        G.lib_off = new_out + (G.lib_off - old_out);
+        G.pts_off = pts + (G.pts_off - R.pts_off);
+        G.pj_off = pj + (G.pj_off - R.pj_off);
+        if (G.sorted) w.max_sorted_n_e = std::max(w.max_sorted_n_e, G.n_e);
+        gather.push_back(G);
+      }
+      p.rz_sample[r] = it->second;
+      R.pts_off = pts;
+      R.pj_off = pj;
+      pts += (int64_t)R.l_eff * R.E;
+      pj += R.l_eff;
+    }
+    w.sample_count = (nested ? (int64_t)shuffles.size() : (int64_t)sample.size()) - w.sample_first;
+    w.gather_count = (int64_t)gather.size() - w.gather_first;
+    w.pool_bytes = (uint64_t)(lib + pj + scr) * 4 + (uint64_t)pts * 4;
+    p.waves.push_back(w);
+    max_lib = std::max(max_lib, lib);
+    max_pts = std::max(max_pts, pts);
+    max_pj = std::max(max_pj, pj);
+    max_scr = std::max(max_scr, scr);
+  }
+  p.wave_rz_first.push_back((int64_t)p.wave_rz.size());
+  if (nested)
+    p.nested = std::move(shuffles);
+  else
+    p.sample = std::move(sample);
+  p.gather = std::move(gather);
+  p.n_lib = max_lib;
+  p.n_pts = max_pts;
+  p.n_pj = max_pj;
+  if (nested) p.n_scratch = max_scr;
+}
+
+// Waves, then the work items of each wave grouped by E (one launch each),
+// the costliest first within a group: a scan costs n_query * l_eff pairs, a
+// table walk about n_query * (E+1) n_e / l_eff row entries.
 static void order_items(Plan& p) {
+  split_waves(p);
   auto cost = [&](const Realization& R) {
     return R.table_off >= 0 ? (double)R.n_query * (R.E + 1) * R.n_e / R.l_eff / 8.0
                             : (double)R.n_query * R.l_eff;
   };
-  std::vector<int32_t> order(p.rz.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    if (p.rz[a].E != p.rz[b].E) return p.rz[a].E < p.rz[b].E;
-    return cost(p.rz[a]) > cost(p.rz[b]);
-  });
-  for (int32_t idx : order) {
-    const Realization& R = p.rz[idx];
-    if (p.e_count[R.E] == 0) p.e_first[R.E] = (int)p.items.size();
-    for (int t = 0; t < R.n_tiles; ++t) p.items.push_back({idx, t});
-    p.e_count[R.E] += R.n_tiles;
+  for (size_t w = 0; w < p.waves.size(); ++w) {
+    std::vector<int32_t> order(p.wave_rz.begin() + p.wave_rz_first[w],
+                               p.wave_rz.begin() + p.wave_rz_first[w + 1]);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      if (p.rz[a].E != p.rz[b].E) return p.rz[a].E < p.rz[b].E;
+      return cost(p.rz[a]) > cost(p.rz[b]);
+    });
+    p.waves[w].launch_first = (int32_t)p.launches.size();
+    for (int32_t idx : order) {
+      const Realization& R = p.rz[idx];
+      if (p.launches.size() == (size_t)p.waves[w].launch_first || p.launches.back().E != R.E)
+        p.launches.push_back({R.E, (int32_t)p.items.size(), 0});
+      for (int t = 0; t < R.n_tiles; ++t) p.items.push_back({idx, t});
+      p.launches.back().count += R.n_tiles;
+      if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
+    }
+    p.waves[w].launch_count = (int32_t)p.launches.size() - p.waves[w].launch_first;
   }
-  if (p.items.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many work items");
 }
 
 // Nested libraries: per (E, tau) the distinct library sizes, sorted, split
@@ -182,6 +348,8 @@ static Plan make_plan_nested(const Spec& s) {
           R.table_off = -1;
           R.n_seg = n_seg;
           R.seg_off = seg_off;
+          p.rz_sample.push_back((int64_t)p.nested.size() - 1);
+          p.rz_gather.push_back((int64_t)p.gather.size());
           for (int k = 0; k < n_seg; ++k) {
             const int64_t b0 = p.segs[seg_off + k], b1 = p.segs[seg_off + k + 1];
             GatherJob gj{};
@@ -331,6 +499,7 @@ static Plan make_plan_shared(const Spec& s) {
           p.n_slots += (int64_t)R.n_tiles * Emax;
           p.rz.push_back(R);
           p.rz_sample.push_back((int64_t)p.sample.size() - 1);
+          p.rz_gather.push_back((int64_t)p.gather.size() - 1);
           // each pair's E_max-coordinate distance is computed once
           double pairs = (double)nc * (double)le;
           if (p.mode == kExclSelf) pairs -= (double)le;
@@ -463,6 +632,7 @@ Plan make_plan(const Spec& s) {
             p.n_slots += R.n_tiles;
             p.rz.push_back(R);
             p.rz_sample.push_back((int64_t)p.sample.size() - 1);
+            p.rz_gather.push_back((int64_t)p.gather.size() - 1);
             // algorithmic work: every (query, candidate) pair but the query itself
             const double nq = (double)R.n_query;
             double pairs = nq * (double)le;
@@ -594,6 +764,7 @@ Plan make_plan_matrix(const Spec& s) {
         p.rz.push_back(R);
         p.self_of.push_back(a);
         p.rz_sample.push_back((int64_t)il * s.r + ri);
+        p.rz_gather.push_back((int64_t)p.gather.size() - 1);
         const double nq = (double)R.n_query;
         double pairs = nq * (double)le;
         if (p.mode == kExclSelf) pairs -= s.query_set ? nq : (double)le;

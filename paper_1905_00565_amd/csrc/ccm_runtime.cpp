@@ -104,7 +104,41 @@ Exec* prepare(ccm_ctx* c, const Spec& s) {
     ex->d_partial.ensure(p.n_slots * sizeof(Moments));
   }
   ex->d_out.ensure(p.n_out * 8);
-  ex->d_counter.ensure(64 * sizeof(int));
+  ex->d_counter.ensure(std::max<size_t>(64, p.launches.size()) * sizeof(int));
+  PlanBuffers& b = ex->buf;
+  b.ingest = ex->d_ingest.as<IngestJob>();
+  b.embed = ex->d_embed.as<EmbedJob>();
+  b.sample = ex->d_sample.as<SampleJob>();
+  b.gather = ex->d_gather.as<GatherJob>();
+  b.rz = ex->d_rz.as<Realization>();
+  b.items = ex->d_items.as<Item>();
+  b.plain_items = ex->d_plain_items.as<Item>();
+  b.orders = ex->d_orders.as<OrderJob>();
+  b.segoff = ex->d_segoff.as<int32_t>();
+  b.s64 = ex->d_s64.as<double>();
+  b.s32 = ex->d_s32.as<float>();
+  b.iota = ex->d_iota.as<int32_t>();
+  b.keys = ex->d_keys.as<uint32_t>();
+  b.keys_out = ex->d_keys_out.as<uint32_t>();
+  b.order = ex->d_order.as<int32_t>();
+  b.sort_temp = ex->d_sort_temp.p;
+  b.qord = ex->d_qord.as<int32_t>();
+  b.start = ex->d_start.as<int32_t>();
+  b.emb = ex->d_emb.as<float>();
+  b.lib = ex->d_lib.as<int32_t>();
+  b.pts = ex->d_pts.as<float>();
+  b.pj = ex->d_pj.as<int32_t>();
+  b.partial = ex->d_partial.p;
+  b.out = ex->d_out.as<double>();
+  b.counter = ex->d_counter.as<int>();
+  b.self = ex->d_self.as<int32_t>();
+  b.tt = ex->d_tt.as<double>();
+  b.tables = ex->d_tables.as<TableJob>();
+  b.table = ex->d_table.as<int32_t>();
+  b.nested = ex->d_nested.as<NestedJob>();
+  b.shuffle = ex->d_scratch.as<int32_t>();
+  b.segs = ex->d_segs.as<int32_t>();
+  b.rz_fin = ex->d_rz_fin.as<Realization>();
   c->exec = std::move(ex);
   return c->exec.get();
 }
@@ -115,158 +149,119 @@ int persistent_grid(ccm_ctx* c, int n_items) {
   return std::min(g, n_items);
 }
 
-// Queue every launch of a plan on stream st.
-void enqueue(ccm_ctx* c, Exec* ex, hipStream_t st, bool timed) {
-  const Plan& p = ex->plan;
-  HIPCHK(launch_ingest(ex->d_ingest.as<IngestJob>(), (int)p.ingest.size(), p.n64,
-                       ex->d_s64.as<double>(), ex->d_s32.as<float>(), st));
-  HIPCHK(launch_embed(ex->d_embed.as<EmbedJob>(), (int)p.embed.size(), p.max_embed,
-                      ex->d_s32.as<float>(), ex->d_emb.as<float>(), st));
-  if (p.spec.M > 0)
-    HIPCHK(launch_transpose_targets(ex->d_s64.as<double>(), p.spec.M, p.spec.N,
-                                    ex->d_tt.as<double>(), st));
-  HIPCHK(launch_order_keys(ex->d_orders.as<OrderJob>(), p.n_sets, ex->d_s32.as<float>(),
-                           ex->d_keys.as<uint32_t>(), st));
-  HIPCHK(launch_iota_segments(ex->d_iota.as<int32_t>(), p.spec.N, p.n_sets, st));
+// One cross-map launch over items [first, first + n) of b.items (or of
+// b.plain_items), E's kernel variant for the plan's form.
+void launch_items(ccm_ctx* c, const Plan& p, const PlanBuffers& b, const Item* items, int n,
+                  int E, int grid, int* next, int table_ne, hipStream_t st, bool timed) {
+  EvPair ev;
+  if (timed) {
+    ev = take_events(c);
+    HIPCHK(hipEventRecord(ev.a, st));
+  }
+  const Dump nodump{nullptr, nullptr, nullptr};
+  if (p.shared_emax > 0)
+    HIPCHK(launch_crossmap_shared(E, p.mode, grid, b.rz, items, n, next, b.emb, b.pts, b.pj,
+                                  b.qord, b.start, b.s64, static_cast<Moments*>(b.partial),
+                                  p.window, st));
+  else if (!p.nested.empty())
+    HIPCHK(launch_crossmap_nested(E, p.mode, grid, b.rz, items, n, next, b.emb, b.pts, b.pj,
+                                  b.qord, b.start, b.s64, b.segs,
+                                  static_cast<Moments*>(b.partial), p.window, st));
+  else if (p.spec.M > 0)
+    HIPCHK(launch_crossmap_multi(E, p.mode, grid, b.rz, b.self, items, n, next, b.emb, b.pts,
+                                 b.pj, b.qord, b.start, b.tt, p.spec.M, b.partial,
+                                 p.spec.query_set, p.window, b.table, table_ne, st));
+  else
+    HIPCHK(launch_crossmap(E, p.mode, grid, b.rz, items, n, next, b.emb, b.pts, b.pj, b.qord,
+                           b.start, b.s64, static_cast<Moments*>(b.partial), p.spec.query_set,
+                           p.window, nodump, b.table, table_ne, st));
+  if (timed) {
+    HIPCHK(hipEventRecord(ev.b, st));
+    c->ev_pending.push_back(ev);
+  }
+}
+
+}  // namespace
+
+namespace ccmh {
+
+void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
+                  const std::vector<int64_t>& plain_first, hipStream_t st, bool timed) {
+  HIPCHK(launch_ingest(b.ingest, (int)p.ingest.size(), p.n64, b.s64, b.s32, st));
+  HIPCHK(launch_embed(b.embed, (int)p.embed.size(), p.max_embed, b.s32, b.emb, st));
+  if (p.spec.M > 0) HIPCHK(launch_transpose_targets(b.s64, p.spec.M, p.spec.N, b.tt, st));
+  HIPCHK(launch_order_keys(b.orders, p.n_sets, b.s32, b.keys, st));
+  HIPCHK(launch_iota_segments(b.iota, p.spec.N, p.n_sets, st));
   {
     size_t tb = p.sort_temp;
-    HIPCHK(sort_series(ex->d_sort_temp.p, tb, ex->d_keys.as<uint32_t>(),
-                       ex->d_keys_out.as<uint32_t>(), ex->d_iota.as<int32_t>(),
-                       ex->d_order.as<int32_t>(), p.spec.N, p.n_sets,
-                       ex->d_segoff.as<int32_t>(), st));
+    HIPCHK(sort_series(b.sort_temp, tb, b.keys, b.keys_out, b.iota, b.order, p.spec.N,
+                       p.n_sets, b.segoff, st));
   }
-  HIPCHK(launch_query_order(ex->d_embed.as<EmbedJob>(), (int)p.embed.size(),
-                            ex->d_order.as<int32_t>(), ex->d_qord.as<int32_t>(), st));
+  HIPCHK(launch_query_order(b.embed, (int)p.embed.size(), b.order, b.qord, st));
+  for (int E = 1; E <= kMaxE; ++E)
+    HIPCHK(launch_table_build(E, b.tables + p.te_first[E], p.te_count[E], p.te_max_ne[E], b.emb,
+                              b.table, st));
   const bool plain = (p.spec.flags & CCM_FLAG_PLAIN) != 0;
   const bool persistent = (p.spec.flags & CCM_FLAG_PERSISTENT) != 0;
-  const Dump nodump{nullptr, nullptr, nullptr};
-  const int32_t* table = ex->d_table.as<int32_t>();
-  for (int E = 1; E <= kMaxE; ++E)
-    HIPCHK(launch_table_build(E, ex->d_tables.as<TableJob>() + p.te_first[E], p.te_count[E],
-                              p.te_max_ne[E], ex->d_emb.as<float>(), ex->d_table.as<int32_t>(),
-                              st));
   const bool nested = !p.nested.empty();
-  if (!plain) {
-    if (nested)
-      HIPCHK(launch_sample_nested(ex->d_nested.as<NestedJob>(), (int64_t)p.nested.size(),
-                                  ex->d_scratch.as<int32_t>(), ex->d_lib.as<int32_t>(), st));
-    else
-      HIPCHK(launch_sample(ex->d_sample.as<SampleJob>(), (int64_t)p.sample.size(),
-                           ex->d_lib.as<int32_t>(), st));
-    HIPCHK(launch_gather(ex->d_gather.as<GatherJob>(), (int64_t)p.gather.size(),
-                         p.max_sorted_n_e, ex->d_emb.as<float>(), ex->d_lib.as<int32_t>(),
-                         ex->d_order.as<int32_t>(), ex->d_pts.as<float>(),
-                         ex->d_pj.as<int32_t>(), ex->d_start.as<int32_t>(), st));
-    for (int E = 1; E <= kMaxE; ++E) {
-      const int n = p.e_count[E];
-      if (n == 0) continue;
-      int grid = n;
-      int* next = nullptr;
-      if (persistent) {
-        grid = persistent_grid(c, n);
-        next = ex->d_counter.as<int>() + E;
-        HIPCHK(launch_zero_int(next, 1, st));
-      }
-      EvPair ev;
-      if (timed) {
-        ev = take_events(c);
-        HIPCHK(hipEventRecord(ev.a, st));
-      }
-      if (p.shared_emax > 0)
-        HIPCHK(launch_crossmap_shared(E, p.mode, grid, ex->d_rz.as<Realization>(),
-                                      ex->d_items.as<Item>() + p.e_first[E], n, next,
-                                      ex->d_emb.as<float>(), ex->d_pts.as<float>(),
-                                      ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
-                                      ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
-                                      ex->d_partial.as<Moments>(), p.window, st));
-      else if (nested)
-        HIPCHK(launch_crossmap_nested(E, p.mode, grid, ex->d_rz.as<Realization>(),
-                                      ex->d_items.as<Item>() + p.e_first[E], n, next,
-                                      ex->d_emb.as<float>(), ex->d_pts.as<float>(),
-                                      ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
-                                      ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
-                                      ex->d_segs.as<int32_t>(), ex->d_partial.as<Moments>(),
-                                      p.window, st));
-      else if (p.spec.M > 0)
-        HIPCHK(launch_crossmap_multi(E, p.mode, grid, ex->d_rz.as<Realization>(),
-                                     ex->d_self.as<int32_t>(),
-                                     ex->d_items.as<Item>() + p.e_first[E], n, next,
-                                     ex->d_emb.as<float>(), ex->d_pts.as<float>(),
-                                     ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
-                                     ex->d_start.as<int32_t>(), ex->d_tt.as<double>(),
-                                     p.spec.M, ex->d_partial.p, p.spec.query_set,
-                                     p.window, table, p.e_table_ne[E], st));
+  // each wave draws and gathers its libraries into the shared pools, then
+  // runs its cross-map launches (one per E)
+  for (size_t wi = 0; wi < p.waves.size(); ++wi) {
+    const Wave& w = p.waves[wi];
+    if (!plain) {
+      if (nested)
+        HIPCHK(launch_sample_nested(b.nested + w.sample_first, w.sample_count, b.shuffle, b.lib,
+                                    st));
       else
-        HIPCHK(launch_crossmap(E, p.mode, grid, ex->d_rz.as<Realization>(),
-                               ex->d_items.as<Item>() + p.e_first[E], n, next,
-                               ex->d_emb.as<float>(), ex->d_pts.as<float>(),
-                               ex->d_pj.as<int32_t>(), ex->d_qord.as<int32_t>(),
-                               ex->d_start.as<int32_t>(), ex->d_s64.as<double>(),
-                               ex->d_partial.as<Moments>(), p.spec.query_set, p.window,
-                               nodump, table, p.e_table_ne[E], st));
-      if (timed) {
-        HIPCHK(hipEventRecord(ev.b, st));
-        c->ev_pending.push_back(ev);
+        HIPCHK(launch_sample(b.sample + w.sample_first, w.sample_count, b.lib, st));
+      HIPCHK(launch_gather(b.gather + w.gather_first, w.gather_count, w.max_sorted_n_e, b.emb,
+                           b.lib, b.order, b.pts, b.pj, b.start, st));
+      for (int li = w.launch_first; li < w.launch_first + w.launch_count; ++li) {
+        const Launch& L = p.launches[li];
+        int grid = L.count;
+        int* next = nullptr;
+        if (persistent) {
+          grid = persistent_grid(c, L.count);
+          next = b.counter + li;
+          HIPCHK(launch_zero_int(next, 1, st));
+        }
+        launch_items(c, p, b, b.items + L.first, L.count, L.E, grid, next, p.e_table_ne[L.E],
+                     st, timed);
       }
-    }
-  } else {
-    // the unbatched baseline: sampler, gather and cross-map launched per
-    // realization
-    std::vector<char> sampled(p.sample.size(), 0);
-    for (size_t r = 0; r < p.rz.size(); ++r) {
-      const Realization& R = p.rz[r];
-      const int64_t sj = p.rz_sample[r];
-      if (!sampled[sj]) {
-        HIPCHK(launch_sample(ex->d_sample.as<SampleJob>() + sj, 1, ex->d_lib.as<int32_t>(), st));
-        sampled[sj] = 1;
-      }
-      HIPCHK(launch_gather(ex->d_gather.as<GatherJob>() + r, 1,
-                           p.gather[r].sorted ? p.gather[r].n_e : 0, ex->d_emb.as<float>(),
-                           ex->d_lib.as<int32_t>(), ex->d_order.as<int32_t>(),
-                           ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
-                           ex->d_start.as<int32_t>(), st));
-      EvPair ev;
-      if (timed) {
-        ev = take_events(c);
-        HIPCHK(hipEventRecord(ev.a, st));
-      }
-      if (p.spec.M > 0)
-        HIPCHK(launch_crossmap_multi(R.E, p.mode, R.n_tiles, ex->d_rz.as<Realization>(),
-                                     ex->d_self.as<int32_t>(),
-                                     ex->d_plain_items.as<Item>() + ex->plain_first[r],
-                                     R.n_tiles, nullptr, ex->d_emb.as<float>(),
-                                     ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
-                                     ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
-                                     ex->d_tt.as<double>(), p.spec.M,
-                                     ex->d_partial.p, p.spec.query_set, p.window, table,
-                                     R.table_off >= 0 ? R.n_e : 0, st));
-      else
-        HIPCHK(launch_crossmap(R.E, p.mode, R.n_tiles, ex->d_rz.as<Realization>(),
-                               ex->d_plain_items.as<Item>() + ex->plain_first[r],
-                               R.n_tiles, nullptr, ex->d_emb.as<float>(),
-                               ex->d_pts.as<float>(), ex->d_pj.as<int32_t>(),
-                               ex->d_qord.as<int32_t>(), ex->d_start.as<int32_t>(),
-                               ex->d_s64.as<double>(), ex->d_partial.as<Moments>(),
-                               p.spec.query_set, p.window, nodump, table,
-                               R.table_off >= 0 ? R.n_e : 0, st));
-      if (timed) {
-        HIPCHK(hipEventRecord(ev.b, st));
-        c->ev_pending.push_back(ev);
+    } else {
+      // the unbatched baseline: sampler, gather and cross-map launched per
+      // realization
+      std::vector<char> sampled(w.sample_count, 0);
+      for (int64_t k = p.wave_rz_first[wi]; k < p.wave_rz_first[wi + 1]; ++k) {
+        const int32_t r = p.wave_rz[k];
+        const Realization& R = p.rz[r];
+        const int64_t sj = p.rz_sample[r];
+        if (!sampled[sj - w.sample_first]) {
+          HIPCHK(launch_sample(b.sample + sj, 1, b.lib, st));
+          sampled[sj - w.sample_first] = 1;
+        }
+        const GatherJob& G = p.gather[p.rz_gather[r]];
+        HIPCHK(launch_gather(b.gather + p.rz_gather[r], 1, G.sorted ? G.n_e : 0, b.emb, b.lib,
+                             b.order, b.pts, b.pj, b.start, st));
+        launch_items(c, p, b, b.plain_items + plain_first[r], R.n_tiles, R.E, R.n_tiles,
+                     nullptr, R.table_off >= 0 ? R.n_e : 0, st, timed);
       }
     }
   }
   if (p.spec.M > 0)
-    HIPCHK(launch_finalize_multi(ex->d_rz.as<Realization>(), ex->d_self.as<int32_t>(),
-                                 (int64_t)p.rz.size(), p.spec.M, ex->d_partial.p,
-                                 (int64_t)p.spec.L.size() * p.spec.r, ex->d_out.as<double>(),
-                                 st));
+    HIPCHK(launch_finalize_multi(b.rz, b.self, (int64_t)p.rz.size(), p.spec.M, b.partial,
+                                 (int64_t)p.spec.L.size() * p.spec.r, b.out, st));
   else if (!p.rz_fin.empty())
-    HIPCHK(launch_finalize(ex->d_rz_fin.as<Realization>(), (int64_t)p.rz_fin.size(),
-                           ex->d_partial.as<Moments>(), ex->d_out.as<double>(), st));
+    HIPCHK(launch_finalize(b.rz_fin, (int64_t)p.rz_fin.size(),
+                           static_cast<const Moments*>(b.partial), b.out, st));
   else
-    HIPCHK(launch_finalize(ex->d_rz.as<Realization>(), (int64_t)p.rz.size(),
-                           ex->d_partial.as<Moments>(), ex->d_out.as<double>(), st));
+    HIPCHK(launch_finalize(b.rz, (int64_t)p.rz.size(), static_cast<const Moments*>(b.partial),
+                           b.out, st));
 }
+
+}  // namespace ccmh
+
+namespace {
 
 // Run a prepared plan on stream st: series already in ex->d_s64.
 void run(ccm_ctx* c, Exec* ex, hipStream_t st) {
@@ -279,7 +274,7 @@ void run(ccm_ctx* c, Exec* ex, hipStream_t st) {
       HIPCHK(hipStreamSynchronize(cap));
       HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
       try {
-        enqueue(c, ex, cap, false);
+        enqueue_plan(c, ex->plan, ex->buf, ex->plain_first, cap, false);
       } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(cap, &g);
@@ -294,9 +289,10 @@ void run(ccm_ctx* c, Exec* ex, hipStream_t st) {
     }
     HIPCHK(hipGraphLaunch(ex->graph, st));
   } else {
-    enqueue(c, ex, st, c->profiling);
+    enqueue_plan(c, ex->plan, ex->buf, ex->plain_first, st, c->profiling);
   }
   if (c->profiling) {
+    c->prof.waves += (double)p.waves.size();
     c->prof.pairs += p.pairs;
     c->prof.flops += p.flops;
     c->prof.predictions += p.preds;
@@ -337,6 +333,7 @@ ccm_status ccm_create(int device, ccm_ctx** out) {
     return CCM_E_DEVICE;
   }
   c->num_cus = prop.multiProcessorCount;
+  c->wave_limit = default_wave_limit(prop.totalGlobalMem);
   *out = c;
   return CCM_OK;
 }
@@ -363,6 +360,17 @@ void ccm_destroy(ccm_ctx* c) {
 
 const char* ccm_last_error(const ccm_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
 
+ccm_status ccm_set_wave_limit(ccm_ctx* c, uint64_t bytes) {
+  return guarded(c, [&] {
+    if (bytes == 0) {
+      hipDeviceProp_t prop;
+      HIPCHK(hipGetDeviceProperties(&prop, c->device));
+      bytes = default_wave_limit(prop.totalGlobalMem);
+    }
+    c->wave_limit = bytes;
+  });
+}
+
 ccm_status ccm_sweep(ccm_ctx* c, const double* X, const double* Y, int64_t N,
                      const int32_t* E, int32_t nE, const int32_t* tau, int32_t ntau,
                      const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
@@ -370,6 +378,7 @@ ccm_status ccm_sweep(ccm_ctx* c, const double* X, const double* Y, int64_t N,
   return guarded(c, [&] {
     if (!rho) fail(CCM_E_INVAL, "rho is NULL");
     Spec s = make_spec(N, E, nE, tau, ntau, L, nL, r, seed, opts);
+    s.wave_limit = c->wave_limit;
     check_host_series(X, N, "X");
     check_host_series(Y, N, "Y");
     Exec* ex = prepare(c, s);
@@ -387,6 +396,7 @@ ccm_status ccm(ccm_ctx* c, const double* X, const double* Y, int64_t N, int32_t 
   return guarded(c, [&] {
     if (!rho_xy || !rho_yx) fail(CCM_E_INVAL, "rho output is NULL");
     Spec s = make_spec(N, &E, 1, &tau, 1, L, nL, r, seed, opts);
+    s.wave_limit = c->wave_limit;
     check_host_series(X, N, "X");
     check_host_series(Y, N, "Y");
     Exec* ex = prepare(c, s);
@@ -410,6 +420,7 @@ ccm_status ccm_sweep_dev(ccm_ctx* c, const double* X, const double* Y, int64_t N
   return guarded(c, [&] {
     if (!X || !Y || !rho) fail(CCM_E_INVAL, "NULL device pointer");
     Spec s = make_spec(N, E, nE, tau, ntau, L, nL, r, seed, opts);
+    s.wave_limit = c->wave_limit;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Exec* ex = prepare(c, s);
     HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyDeviceToDevice, st));
@@ -426,6 +437,7 @@ ccm_status ccm_dev(ccm_ctx* c, const double* X, const double* Y, int64_t N, int3
   return guarded(c, [&] {
     if (!X || !Y || !rho_xy || !rho_yx) fail(CCM_E_INVAL, "NULL device pointer");
     Spec s = make_spec(N, &E, 1, &tau, 1, L, nL, r, seed, opts);
+    s.wave_limit = c->wave_limit;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Exec* ex = prepare(c, s);
     HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyDeviceToDevice, st));
@@ -446,6 +458,7 @@ ccm_status ccm_matrix(ccm_ctx* c, const double* S, int32_t M, int64_t N, int32_t
   return guarded(c, [&] {
     if (!rho) fail(CCM_E_INVAL, "rho is NULL");
     Spec s = make_matrix_spec(M, N, E, tau, L, nL, r, seed, opts);
+    s.wave_limit = c->wave_limit;
     check_host_series(S, (int64_t)M * N, "S");
     Exec* ex = prepare(c, s);
     HIPCHK(hipMemcpyAsync(ex->d_s64.p, S, (size_t)M * N * 8, hipMemcpyHostToDevice, c->stream));
@@ -461,6 +474,7 @@ ccm_status ccm_matrix_dev(ccm_ctx* c, const double* S, int32_t M, int64_t N, int
   return guarded(c, [&] {
     if (!S || !rho) fail(CCM_E_INVAL, "NULL device pointer");
     Spec s = make_matrix_spec(M, N, E, tau, L, nL, r, seed, opts);
+    s.wave_limit = c->wave_limit;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Exec* ex = prepare(c, s);
     HIPCHK(hipMemcpyAsync(ex->d_s64.p, S, (size_t)M * N * 8, hipMemcpyDeviceToDevice, st));

@@ -74,10 +74,14 @@ class RangeAlloc {
 
 enum JobState { kPending, kActive, kDone, kCancelled, kFailed };
 
-// Byte layout of one job's region in the arena.
+// Byte layout of one job's region in the arena.  The series and the
+// descriptor arrays come first, as one block [0, upload): the job's pinned
+// staging block holds the same bytes at the same offsets, so one copy
+// uploads them.
 struct Layout {
   uint64_t s64, s32, iota, keys, keys_out, order, temp, qord, emb, lib, pts, pj, out, table;
   uint64_t d_ingest, d_embed, d_sample, d_gather, d_segoff, d_orders, d_tables;
+  uint64_t upload;   // bytes of the series and descriptor block
   uint64_t bytes;
 };
 
@@ -92,6 +96,14 @@ Layout layout_of(const Plan& p) {
     return at;
   };
   l.s64 = take(p.n64 * 8);
+  l.d_ingest = take(p.ingest.size() * sizeof(IngestJob));
+  l.d_embed = take(p.embed.size() * sizeof(EmbedJob));
+  l.d_sample = take(p.sample.size() * sizeof(SampleJob));
+  l.d_gather = take(p.gather.size() * sizeof(GatherJob));
+  l.d_segoff = take(p.seg_off.size() * 4);
+  l.d_orders = take(p.orders.size() * sizeof(OrderJob));
+  l.d_tables = take(p.tables.size() * sizeof(TableJob));
+  l.upload = o;
   l.s32 = take(p.n32 * 4);
   l.iota = take(p.n_ord * 4);
   l.keys = take(p.n_ord * 4);
@@ -105,13 +117,6 @@ Layout layout_of(const Plan& p) {
   l.pj = take(p.n_pj * 4);
   l.out = take(p.n_out * 8);
   l.table = take(p.n_table * 4);
-  l.d_ingest = take(p.ingest.size() * sizeof(IngestJob));
-  l.d_embed = take(p.embed.size() * sizeof(EmbedJob));
-  l.d_sample = take(p.sample.size() * sizeof(SampleJob));
-  l.d_gather = take(p.gather.size() * sizeof(GatherJob));
-  l.d_segoff = take(p.seg_off.size() * 4);
-  l.d_orders = take(p.orders.size() * sizeof(OrderJob));
-  l.d_tables = take(p.tables.size() * sizeof(TableJob));
   l.bytes = o;
   return l;
 }
@@ -120,7 +125,11 @@ struct Job {
   uint64_t ticket = 0;
   Plan plan;
   Layout lay{};
-  std::vector<double> X, Y;
+  // Pinned staging, filled at submit: [0, lay.upload) mirrors the region's
+  // series and descriptor block, then the realizations (rebased at
+  // admission), then the rho copied back.
+  char* staging = nullptr;
+  uint64_t staging_rz = 0, staging_rho = 0;
   JobState state = kPending;
   ccm_status status = CCM_OK;
   // resources (valid while active)
@@ -134,9 +143,22 @@ struct Job {
   // left the queue): until then ccm_wait keeps waiting and ccm_result
   // answers CCM_E_BUSY, whatever the state says.
   bool retired = false;
+  // per epoch stream: an epoch on it has waited for the job's preparation
+  // (epochs on the two streams run concurrently, so each stream waits once)
+  bool prep_waited[2] = {false, false};
+  hipEvent_t prep_ev = nullptr;  // after its upload and preparation kernels
   hipEvent_t done_ev = nullptr;
-  double* rho_host = nullptr;    // pinned [n_out]
+  double* rho_host = nullptr;    // pinned [n_out], inside staging
   double t_submit = 0, t_admit = 0, t_done = 0;
+
+  Job() = default;
+  Job(const Job&) = delete;
+  Job& operator=(const Job&) = delete;
+  ~Job() {
+    if (staging) (void)hipHostFree(staging);
+    if (prep_ev) (void)hipEventDestroy(prep_ev);
+    if (done_ev) (void)hipEventDestroy(done_ev);
+  }
 };
 
 // Cost of one work item in VALU lane operations: tile queries x library x (2E+1).
@@ -150,9 +172,9 @@ double item_cost(const Realization& R, int tile, int qt) {
 struct ccm_server {
   ccm_ctx* ctx = nullptr;
   int device = 0;
-  hipStream_t stream = nullptr;      // job preparation and finalize
+  hipStream_t pstream = nullptr;     // job upload and preparation
+  hipStream_t fstream = nullptr;     // job finalize and result copy
   hipStream_t estream[2] = {nullptr, nullptr};   // epochs alternate between these
-  hipEvent_t prep_ev = nullptr;      // after the latest preparation
   double epoch_ms = 20.0;
   int max_jobs = 64;
   // device memory
@@ -220,19 +242,46 @@ T* at(const ccm_server* s, uint64_t byte_off) {
   return reinterpret_cast<T*>(static_cast<char*>(s->arena.p) + byte_off);
 }
 
-// Upload a job's inputs and descriptors and queue its preparation kernels.
+// Fill a job's pinned staging block at submit: series and descriptors at
+// their region offsets, then the realizations (region-relative until
+// admission).
+void stage_job(Job& j, const double* X, const double* Y) {
+  const Plan& p = j.plan;
+  const Layout& L = j.lay;
+  char* b = j.staging;
+  auto put = [&](uint64_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(b + off, src, bytes);
+  };
+  const int64_t N = p.spec.N;
+  put(L.s64, X, N * 8);
+  put(L.s64 + N * 8, Y, N * 8);
+  put(L.d_ingest, p.ingest.data(), p.ingest.size() * sizeof(IngestJob));
+  put(L.d_embed, p.embed.data(), p.embed.size() * sizeof(EmbedJob));
+  put(L.d_sample, p.sample.data(), p.sample.size() * sizeof(SampleJob));
+  put(L.d_gather, p.gather.data(), p.gather.size() * sizeof(GatherJob));
+  put(L.d_segoff, p.seg_off.data(), p.seg_off.size() * 4);
+  put(L.d_orders, p.orders.data(), p.orders.size() * sizeof(OrderJob));
+  put(L.d_tables, p.tables.data(), p.tables.size() * sizeof(TableJob));
+  put(j.staging_rz, p.rz.data(), p.rz.size() * sizeof(Realization));
+}
+
+// At admission: rebase the staged descriptors to the job's region and slots,
+// upload them with two asynchronous copies from the pinned staging, and
+// queue the preparation kernels; all on the preparation stream, ending with
+// the job's prep_ev.
 void start_job(ccm_server* s, Job& j) {
   const Plan& p = j.plan;
   const Layout& L = j.lay;
   const uint64_t R0 = j.region;
-  hipStream_t st = s->stream;
+  hipStream_t st = s->pstream;
   const int64_t N = p.spec.N;
   // the gather writes scan starts into the server-wide slot space
-  std::vector<GatherJob> gj = p.gather;
-  for (auto& g : gj) g.start_off += (int64_t)j.slot0 * kWaves;
+  GatherJob* gj = reinterpret_cast<GatherJob*>(j.staging + L.d_gather);
+  for (size_t k = 0; k < p.gather.size(); ++k) gj[k].start_off += (int64_t)j.slot0 * kWaves;
   // realizations rebased to arena-wide offsets
-  std::vector<Realization> rz = p.rz;
-  for (auto& R : rz) {
+  Realization* rz = reinterpret_cast<Realization*>(j.staging + j.staging_rz);
+  for (size_t k = 0; k < p.rz.size(); ++k) {
+    Realization& R = rz[k];
     R.emb_off += (int64_t)((R0 + L.emb) / 4);
     R.pts_off += (int64_t)((R0 + L.pts) / 4);
     R.pj_off += (int64_t)((R0 + L.pj) / 4);
@@ -243,34 +292,14 @@ void start_job(ccm_server* s, Job& j) {
   }
   // distance indexing tables, rebased the same way (their extents within
   // the job's embedding and table pools were checked at submit)
-  std::vector<TableJob> tj = p.tables;
-  for (auto& t : tj) {
-    t.emb_off += (int64_t)((R0 + L.emb) / 4);
-    t.out_off += (int64_t)((R0 + L.table) / 4);
+  TableJob* tj = reinterpret_cast<TableJob*>(j.staging + L.d_tables);
+  for (size_t k = 0; k < p.tables.size(); ++k) {
+    tj[k].emb_off += (int64_t)((R0 + L.emb) / 4);
+    tj[k].out_off += (int64_t)((R0 + L.table) / 4);
   }
-  HIPCHK(hipMemcpy(at<char>(s, R0 + L.s64), j.X.data(), N * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(at<char>(s, R0 + L.s64) + N * 8, j.Y.data(), N * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_ingest), p.ingest.data(),
-                   p.ingest.size() * sizeof(IngestJob), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_embed), p.embed.data(),
-                   p.embed.size() * sizeof(EmbedJob), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_sample), p.sample.data(),
-                   p.sample.size() * sizeof(SampleJob), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_gather), gj.data(), gj.size() * sizeof(GatherJob),
-                   hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_segoff), p.seg_off.data(), p.seg_off.size() * 4,
-                   hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_orders), p.orders.data(),
-                   p.orders.size() * sizeof(OrderJob), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(s->rz_table.as<Realization>() + j.rz0, rz.data(),
-                   rz.size() * sizeof(Realization), hipMemcpyHostToDevice));
-  if (!tj.empty())
-    HIPCHK(hipMemcpy(at<char>(s, R0 + L.d_tables), tj.data(), tj.size() * sizeof(TableJob),
-                     hipMemcpyHostToDevice));
-  j.X.clear();
-  j.X.shrink_to_fit();
-  j.Y.clear();
-  j.Y.shrink_to_fit();
+  HIPCHK(hipMemcpyAsync(at<char>(s, R0), j.staging, L.upload, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->rz_table.as<Realization>() + j.rz0, rz,
+                        p.rz.size() * sizeof(Realization), hipMemcpyHostToDevice, st));
 
   HIPCHK(launch_ingest(at<IngestJob>(s, R0 + L.d_ingest), (int)p.ingest.size(), p.n64,
                        at<double>(s, R0 + L.s64), at<float>(s, R0 + L.s32), st));
@@ -296,19 +325,21 @@ void start_job(ccm_server* s, Job& j) {
                        p.max_sorted_n_e, at<float>(s, R0 + L.emb), at<int32_t>(s, R0 + L.lib),
                        at<int32_t>(s, R0 + L.order), at<float>(s, R0 + L.pts),
                        at<int32_t>(s, R0 + L.pj), s->slots_start.as<int32_t>(), st));
+  HIPCHK(hipEventRecord(j.prep_ev, st));
 }
 
 // Queue the merge of a job's moments and the copy of its rho to the host.
 void finish_job(ccm_server* s, Job& j) {
   const Plan& p = j.plan;
   // the job's items may be in the latest epoch of either epoch stream
-  for (int b = 0; b < 2; ++b) HIPCHK(hipStreamWaitEvent(s->stream, s->epoch_ev[b], 0));
+  hipStream_t st = s->fstream;
+  for (int b = 0; b < 2; ++b) HIPCHK(hipStreamWaitEvent(st, s->epoch_ev[b], 0));
   HIPCHK(launch_finalize(s->rz_table.as<Realization>() + j.rz0, (int64_t)p.rz.size(),
                          s->slots_partial.as<Moments>(), at<double>(s, j.region + j.lay.out),
-                         s->stream));
+                         st));
   HIPCHK(hipMemcpyAsync(j.rho_host, at<double>(s, j.region + j.lay.out), p.n_out * 8,
-                        hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipEventRecord(j.done_ev, s->stream));
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(j.done_ev, st));
   j.finishing = true;
 }
 
@@ -353,7 +384,6 @@ void scheduler_loop(ccm_server* s) {
         j.t_admit = s->now();
         s->active.push_back(j.ticket);
         start_job(s, j);
-        HIPCHK(hipEventRecord(s->prep_ev, s->stream));
       }
       // 3. build an epoch: items of admitted jobs, oldest first, up to the
       // budget.  Two epochs may be in flight: this buffer's previous epoch is
@@ -384,12 +414,16 @@ void scheduler_loop(ccm_server* s) {
       double cost = 0.0;
       std::map<GroupKey, std::vector<Item>> groups;
       std::map<GroupKey, int> group_table_ne;   // largest n_e a group's items walk
-      std::vector<Job*> completes;
+      std::vector<Job*> completes, first_epoch;
       size_t n_items = 0;
       for (uint64_t t : s->active) {
         Job& j = *s->jobs[t];
         if (j.finishing || j.state == kCancelled) continue;
         const Plan& p = j.plan;
+        if (!j.prep_waited[buf]) {
+          first_epoch.push_back(&j);   // its preparation must precede this epoch
+          j.prep_waited[buf] = true;
+        }
         const int E = p.spec.E[0];
         const int qt = kBlock * crossmap_queries_per_lane(E);
         const GroupKey key{E, p.mode, p.spec.query_set, p.window};
@@ -407,13 +441,15 @@ void scheduler_loop(ccm_server* s) {
         if (j.next_item == p.items.size()) completes.push_back(&j);
         if ((cost >= budget && n_items >= s->min_items) || n_items >= s->items_cap) break;
       }
-      // jobs cancelled while active finish once their in-flight items are done
+      // jobs cancelled while active finish once their in-flight preparation
+      // and items are done (their region is reused after that)
       for (uint64_t t : s->active) {
         Job& j = *s->jobs[t];
         if (j.state == kCancelled && !j.finishing) {
+          HIPCHK(hipStreamWaitEvent(s->fstream, j.prep_ev, 0));
           for (int b = 0; b < 2; ++b)
-            HIPCHK(hipStreamWaitEvent(s->stream, s->epoch_ev[b], 0));
-          HIPCHK(hipEventRecord(j.done_ev, s->stream));
+            HIPCHK(hipStreamWaitEvent(s->fstream, s->epoch_ev[b], 0));
+          HIPCHK(hipEventRecord(j.done_ev, s->fstream));
           j.finishing = true;
         }
       }
@@ -441,7 +477,7 @@ void scheduler_loop(ccm_server* s) {
         pos += kv.second.size();
       }
       hipStream_t es = s->estream[buf];
-      HIPCHK(hipStreamWaitEvent(es, s->prep_ev, 0));   // inputs of newly admitted jobs
+      for (Job* j : first_epoch) HIPCHK(hipStreamWaitEvent(es, j->prep_ev, 0));
       HIPCHK(hipMemcpyAsync(s->items_dev[buf].p, s->items_host[buf], pos * sizeof(Item),
                             hipMemcpyHostToDevice, es));
       HIPCHK(hipEventRecord(s->epoch_ev0[buf], es));
@@ -531,18 +567,17 @@ ccm_status ccm_server_create(ccm_ctx* c, const ccm_server_cfg* cfg, ccm_server**
       HIPCHK(hipEventCreate(&s->epoch_ev[b]));
       HIPCHK(hipEventCreate(&s->epoch_ev0[b]));
     }
-    HIPCHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&s->pstream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&s->fstream, hipStreamNonBlocking));
     for (int b = 0; b < 2; ++b) {
       HIPCHK(hipStreamCreateWithFlags(&s->estream[b], hipStreamNonBlocking));
       HIPCHK(hipEventRecord(s->epoch_ev[b], s->estream[b]));   // waitable from the start
     }
-    HIPCHK(hipEventCreate(&s->prep_ev));
     {
       hipDeviceProp_t prop;
       HIPCHK(hipGetDeviceProperties(&prop, c->device));
       s->min_items = (size_t)std::max(1, prop.multiProcessorCount) * 32;
     }
-    HIPCHK(hipEventRecord(s->prep_ev, s->stream));
   } catch (const Fail& e) {
     {
       std::lock_guard<std::mutex> lock(c->mu);
@@ -552,7 +587,10 @@ ccm_status ccm_server_create(ccm_ctx* c, const ccm_server_cfg* cfg, ccm_server**
       if (s->items_host[b]) (void)hipHostFree(s->items_host[b]);
       if (s->epoch_ev[b]) (void)hipEventDestroy(s->epoch_ev[b]);
       if (s->epoch_ev0[b]) (void)hipEventDestroy(s->epoch_ev0[b]);
+      if (s->estream[b]) (void)hipStreamDestroy(s->estream[b]);
     }
+    if (s->pstream) (void)hipStreamDestroy(s->pstream);
+    if (s->fstream) (void)hipStreamDestroy(s->fstream);
     return e.status;
   }
   ccm_server* raw = s.release();
@@ -592,10 +630,15 @@ ccm_status ccm_submit(ccm_server* s, const ccm_job* job, uint64_t* ticket) {
         j->plan.rz.size() > s->rz_alloc.capacity())
       fail(CCM_E_NOMEM, "job needs " + std::to_string(j->lay.bytes) +
                             " device bytes, more than the server's budget");
-    j->X.assign(job->X, job->X + job->N);
-    j->Y.assign(job->Y, job->Y + job->N);
+    // pinned staging: the region's upload block, the realizations, the rho
+    j->staging_rz = up(j->lay.upload, 256);
+    j->staging_rho = up(j->staging_rz + j->plan.rz.size() * sizeof(Realization), 256);
     HIPCHK(hipSetDevice(s->device));
-    HIPCHK(hipHostMalloc((void**)&j->rho_host, j->plan.n_out * 8, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&j->staging, j->staging_rho + j->plan.n_out * 8,
+                         hipHostMallocDefault));
+    j->rho_host = reinterpret_cast<double*>(j->staging + j->staging_rho);
+    stage_job(*j, job->X, job->Y);
+    HIPCHK(hipEventCreateWithFlags(&j->prep_ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming));
     std::lock_guard<std::mutex> lock(s->mu);
     if (s->stop) fail(CCM_E_BUSY, "server is shutting down");
@@ -660,10 +703,10 @@ ccm_status ccm_result(ccm_server* s, uint64_t ticket, double* rho_xy, double* rh
     stats->device_bytes = j->lay.bytes;
   }
   (void)hipSetDevice(s->device);
-  if (j->rho_host) (void)hipHostFree(j->rho_host);
-  if (j->done_ev) (void)hipEventDestroy(j->done_ev);
-  if (j->state == kDone) return CCM_OK;
-  return j->state == kCancelled ? CCM_E_NOTFOUND : j->status;
+  const ccm_status st = j->state == kDone ? CCM_OK
+                        : (j->state == kCancelled ? CCM_E_NOTFOUND : j->status);
+  j.reset();   // frees its pinned staging and events
+  return st;
 }
 
 ccm_status ccm_cancel(ccm_server* s, uint64_t ticket) {
@@ -700,22 +743,20 @@ void ccm_server_destroy(ccm_server* s) {
   }
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->device);
-  (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->pstream);
+  (void)hipStreamSynchronize(s->fstream);
   for (int b = 0; b < 2; ++b)
     if (s->estream[b]) (void)hipStreamSynchronize(s->estream[b]);
-  for (auto& kv : s->jobs) {
-    if (kv.second->rho_host) (void)hipHostFree(kv.second->rho_host);
-    if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
-  }
+  s->jobs.clear();   // frees each job's pinned staging and events
   for (int b = 0; b < 2; ++b) {
     if (s->items_host[b]) (void)hipHostFree(s->items_host[b]);
     if (s->epoch_ev[b]) (void)hipEventDestroy(s->epoch_ev[b]);
     if (s->epoch_ev0[b]) (void)hipEventDestroy(s->epoch_ev0[b]);
   }
-  (void)hipStreamDestroy(s->stream);
+  (void)hipStreamDestroy(s->pstream);
+  (void)hipStreamDestroy(s->fstream);
   for (int b = 0; b < 2; ++b)
     if (s->estream[b]) (void)hipStreamDestroy(s->estream[b]);
-  if (s->prep_ev) (void)hipEventDestroy(s->prep_ev);
   delete s;
 }
 

@@ -226,6 +226,31 @@ ccm_status ccm_matrix_dev(ccm_ctx *ctx, const double *S, int32_t M, int64_t N,
                           double *rho, void *stream);
 
 /*
+ * No-allocation form of ccm_dev, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, computation and results (bit for bit)
+ * as ccm_dev with no flags; it calls no hipMalloc or hipFree: every device
+ * buffer of the call -- descriptors, series copies, embeddings, visiting
+ * orders, libraries, per-tile moments, rho -- is a range of one static
+ * workspace of CCM_NOALLOC_WORKSPACE_BYTES per device, held from the first
+ * context on that device until the process ends.  The descriptors are
+ * copied from host memory of the call with hipMemcpyAsync (pageable: staged
+ * before the call returns); the rest is queued on `stream` as in ccm_dev.
+ * CCM_E_NOMEM, with a message, when the call needs more than the workspace
+ * holds (about 16 MB for N = 1000, E = 2, ten L to 1000, r = 100);
+ * CCM_E_INVAL for flags other than CCM_FLAG_NO_GRAPH.  Every call on one
+ * device uses the same workspace and leaves its contents there: calls that
+ * overlap on one device (different streams, contexts or host threads
+ * without ordering between them) race; calls ordered on one stream do not.
+ */
+#define CCM_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+ccm_status ccm_dev_noalloc(ccm_ctx *ctx, const double *X, const double *Y, int64_t N,
+                           int32_t E, int32_t tau, const int64_t *L, int32_t nL,
+                           int32_t r, uint64_t seed, const ccm_opts *opts,
+                           double *rho_X_from_MY, double *rho_Y_from_MX,
+                           int64_t *L_eff, void *stream);
+
+/*
  * Served form: continuous batching of independent cross-map jobs (paper
  * Section 3.3: several (L, tau, E) pipelines run concurrently instead of one
  * after the other).  Jobs are queued at submit, admitted in arrival order

@@ -23,7 +23,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIBRARY = os.path.join(PKG, "libccm.so")
 
 ARCH = os.environ.get("CCM_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["ccm_kernels.hip", "ccm_sort.hip", "ccm_plan.cpp", "ccm_runtime.cpp", "ccm_server.cpp"]
+SOURCES = ["ccm_kernels.hip", "ccm_sort.hip", "ccm_noalloc.hip", "ccm_plan.cpp",
+           "ccm_runtime.cpp", "ccm_server.cpp"]
 
 
 def hipcc() -> str:

@@ -38,7 +38,7 @@ CCM_TABLE_WIDTH = 1024
 # Every symbol include/ccm.h declares (checked by the ABI test).
 EXPORTS = [
     "ccm_create", "ccm_destroy", "ccm_last_error", "ccm_set_wave_limit", "ccm", "ccm_sweep",
-    "ccm_matrix", "ccm_dev", "ccm_sweep_dev", "ccm_matrix_dev", "ccm_library",
+    "ccm_matrix", "ccm_dev", "ccm_dev_noalloc", "ccm_sweep_dev", "ccm_matrix_dev", "ccm_library",
     "ccm_nested_library", "ccm_neighbors",
     "ccm_profile_enable", "ccm_profile_read",
     "ccm_server_create", "ccm_submit", "ccm_wait", "ccm_result", "ccm_cancel",
@@ -108,6 +108,7 @@ def lib():
         L.ccm.argtypes = [P, P, P, i64, i32, i32, P, i32, i32, u64, P, P, P, P]
         L.ccm_sweep.argtypes = [P, P, P, i64, P, i32, P, i32, P, i32, i32, u64, P, P]
         L.ccm_dev.argtypes = [P, P, P, i64, i32, i32, P, i32, i32, u64, P, P, P, P, P]
+        L.ccm_dev_noalloc.argtypes = [P, P, P, i64, i32, i32, P, i32, i32, u64, P, P, P, P, P]
         L.ccm_sweep_dev.argtypes = [P, P, P, i64, P, i32, P, i32, P, i32, i32, u64, P, P, P]
         L.ccm_matrix.argtypes = [P, P, i32, i64, i32, i32, P, i32, i32, u64, P, P]
         L.ccm_matrix_dev.argtypes = [P, P, i32, i64, i32, i32, P, i32, i32, u64, P, P, P]
@@ -230,6 +231,20 @@ def ccm_dev(ctx, X, Y, E, tau, L, r, seed, rho_xy, rho_yx, stream=None,
     _check(ctx, lib().ccm_dev(ctx, _dev_ptr(X), _dev_ptr(Y), n, E, tau, _ptr(Ls), len(Ls),
                               r, seed & (2**64 - 1), C.byref(o), _dev_ptr(rho_xy),
                               _dev_ptr(rho_yx), _ptr(le), _stream_ptr(stream)))
+    return le
+
+
+def ccm_dev_noalloc(ctx, X, Y, E, tau, L, r, seed, rho_xy, rho_yx, stream=None,
+                    exclusion_radius=0, query_set=0, flags=0, N=None):
+    """ccm_dev with its device buffers in the library's static workspace."""
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    le = np.empty(len(Ls), dtype=np.int64)
+    n = int(N if N is not None else X.numel())
+    o = _opts(exclusion_radius, query_set, flags)
+    _check(ctx, lib().ccm_dev_noalloc(ctx, _dev_ptr(X), _dev_ptr(Y), n, E, tau, _ptr(Ls),
+                                      len(Ls), r, seed & (2**64 - 1), C.byref(o),
+                                      _dev_ptr(rho_xy), _dev_ptr(rho_yx), _ptr(le),
+                                      _stream_ptr(stream)))
     return le
 
 
@@ -428,6 +443,9 @@ class Context:
 
     def ccm_dev(self, *a, **k):
         return ccm_dev(self.handle, *a, **k)
+
+    def ccm_dev_noalloc(self, *a, **k):
+        return ccm_dev_noalloc(self.handle, *a, **k)
 
     def ccm_sweep_dev(self, *a, **k):
         return ccm_sweep_dev(self.handle, *a, **k)

@@ -90,6 +90,11 @@ namespace ccmh {
 void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
                   const std::vector<int64_t>& plain_first, hipStream_t st, bool timed);
 
+// The static workspace of the no-allocation entry point on the current
+// device: set up once per device (at context creation); false, with a
+// message, if the device has none.
+bool noalloc_setup(int device, std::string* err);
+
 // Run f under the context's lock with HIP errors and exceptions turned into
 // status codes (no exception crosses the C ABI).
 template <class F>

@@ -334,6 +334,11 @@ ccm_status ccm_create(int device, ccm_ctx** out) {
   }
   c->num_cus = prop.multiProcessorCount;
   c->wave_limit = default_wave_limit(prop.totalGlobalMem);
+  if (!noalloc_setup(device, &c->err)) {
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+    return CCM_E_DEVICE;
+  }
   *out = c;
   return CCM_OK;
 }

@@ -9,17 +9,32 @@ E=1..10, tau=1..5, 20 library sizes log-spaced 100..10^4, r=250, both
 directions -- 500 000 rho values and ~5e9 cross-map predictions per step.
 The series are resident in device memory before the timed region starts.
 
+The timed steps replay the call's HIP graph (the form a caller gets).  The
+runtime cannot time events recorded by graph nodes, so the roofline's kernel
+durations come from HIP events around each cross-map launch of a profiled
+pass of the same steps right after (direct launches on the same stream); its
+wall time is reported beside the graph's.
+
 Prints one JSON line: value = cross-map predictions per second, plus
 rho-realizations per second, the roofline of the cross-map kernel (binary32
 flops per pair 3E-1, over the summed HIP-event duration of its launches; HBM
 traffic from the committed counter summary when it matches the kernel
 sources), the other workloads of the method (`workloads`: small coupled map
 with plain vs batched launches, long noisy series, 64-series causal matrix),
-the run-time elasticity study (`elasticity`), the same workloads through the
-paper's distance indexing table (`index_table`), the sweep and long series
-with nested libraries (`nested`), the served form's p50/p99 job
-latency on a Poisson job stream (`served`), and the CPU oracle timed on a
-bounded random sample of the same realizations.
+the sweep's launch forms (`forms`: persistent, no graph, plain vs batched on
+its r = 1 subset), the run-time elasticity study (`elasticity`), the same
+workloads through the paper's distance indexing table (`index_table`), the
+sweep and long series with nested libraries (`nested`), E-sweep sharing
+(`shared_e`), the served form (`served`: capacity against the same jobs one
+after another, p50/p99 job latency at several loads, a binding HBM budget),
+and the CPU oracle timed on a deterministic sample of the same realizations
+(all threads and one core, extrapolated to the workload, and checked against
+the GPU's rho).
+
+    python bench.py --serve-protocol 1
+
+runs only the served form's full protocol (seven loads x 1000 jobs) and
+prints its JSON.
 """
 from __future__ import annotations
 
@@ -79,15 +94,18 @@ def parse():
     ap.add_argument("--r", type=int, default=250, help="realizations per L")
     ap.add_argument("--n", type=int, default=10000, help="series length")
     ap.add_argument("--flags", type=int, default=0, help="CCM_FLAG_* bits")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="wall-clock budget of the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-modulus", type=int, default=1000,
+                    help="CPU oracle sample: realizations whose library stream state is "
+                         "0 mod this (0: skip the CPU baseline)")
     ap.add_argument("--workloads", type=int, default=1,
                     help="1: also time the small, long-series and causal-matrix "
                          "workloads and the elasticity study (0: skip)")
-    ap.add_argument("--serve-jobs", type=int, default=32,
-                    help="jobs in the served leg (0: skip it)")
-    ap.add_argument("--serve-load", type=float, default=0.7,
-                    help="Poisson arrival rate as a fraction of measured capacity")
+    ap.add_argument("--serve-jobs", type=int, default=200,
+                    help="jobs per load point of the served leg (0: skip it)")
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95",
+                    help="Poisson arrival rates as fractions of measured capacity")
+    ap.add_argument("--serve-protocol", type=int, default=0,
+                    help="1: run only the served form's full protocol and print it")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device to device "
                          "once (a plain copy of known size for calibrating the "
@@ -95,40 +113,79 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, budget_s):
-    """The oracle on a seeded random sample of the workload's realizations."""
+def cpu_info():
+    """Host cores and CPU model of the machine running the bench."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"nproc": os.cpu_count(), "affinity": affinity, "model": model}
+
+
+def workload_pairs(w):
+    """(query, candidate) pairs of the whole workload (self excluded)."""
+    tot = 0
+    for e in w.E:
+        for t in w.tau:
+            ne = w.N - (e - 1) * t
+            for l in w.L:
+                tot += 2 * w.r * (ne - 1) * min(l, ne)
+    return tot
+
+
+def cpu_baseline(w, rho_gpu, modulus=1000, single_every=12):
+    """The oracle on a deterministic sample of the workload: the realizations
+    whose library stream state is 0 mod `modulus` (both directions), timed on
+    every host thread, and every `single_every`-th of them on one core; the
+    full workload's CPU time is extrapolated by pair count.  The same sample
+    is checked against the GPU's rho of the last timed step."""
     import oracle
     orc = oracle.default()
     threads = oracle.default_threads()
-    rng = np.random.default_rng(12345)
-    X, Y = w.X, w.Y
-    grid = [(e, t, l) for e in w.E for t in w.tau for l in w.L]
-    done_preds = 0.0
-    done = 0
+    tasks, picks = orc.deterministic_sample(w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed, modulus)
+
+    def cost(ts):
+        preds = pairs = 0
+        for t in ts:
+            ne = w.N - (t[2] - 1) * t[3]
+            preds += ne
+            pairs += (ne - 1) * min(t[4], ne)
+        return preds, pairs
+
+    preds, pairs = cost(tasks)
     t0 = time.perf_counter()
-    from concurrent.futures import ThreadPoolExecutor
-
-    def one(task):
-        e, t, l, ri, d = task
-        S, T = (Y, X) if d == 0 else (X, Y)
-        orc.realization(S, T, e, t, l, ri, w.seed)
-        return w.N - (e - 1) * t        # predictions (every embedded point)
-
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        while time.perf_counter() - t0 < budget_s:
-            batch = []
-            for _ in range(threads):
-                e, t, l = grid[int(rng.integers(len(grid)))]
-                batch.append((e, t, l, int(rng.integers(w.r)), int(rng.integers(2))))
-            for p in ex.map(one, batch):
-                done_preds += p
-                done += 1
+    want = orc.realizations_threaded(tasks, threads)
     el = time.perf_counter() - t0
-    return {"value": done_preds / el, "unit": "predictions/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{done} realizations drawn uniformly at random (seed 12345) from "
-                      f"the {len(grid) * w.r * 2} of the workload, {el:.1f} s on "
-                      f"{threads} threads"}
+    sub = tasks[::single_every]
+    preds1, pairs1 = cost(sub)
+    t0 = time.perf_counter()
+    orc.realizations_threaded(sub, threads=1)
+    el1 = time.perf_counter() - t0
+    got = np.asarray([rho_gpu[p] for p in picks])
+    full = workload_pairs(w)
+    return {"value": preds / el, "unit": "predictions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(tasks)} realizations of the workload's {2 * len(w.E) * len(w.tau) * len(w.L) * w.r} "
+                      f"(library stream state = 0 mod {modulus}, both directions; "
+                      f"{pairs:.3g} pairs), {el:.1f} s on {threads} threads",
+            "single_core": {"value": preds1 / el1, "unit": "predictions/s", "cores": 1,
+                            "sample": f"every {single_every}th of the sample: {len(sub)} "
+                                      f"realizations, {pairs1:.3g} pairs, {el1:.1f} s"},
+            "cpu": cpu_info(),
+            "extrapolated": {"label": "extrapolated by pair count from the sample",
+                             "workload_pairs": full,
+                             "step_seconds_all_threads": el * full / pairs,
+                             "step_seconds_one_core": el1 * full / pairs1},
+            "parity": {"realizations": len(tasks),
+                       "max_abs_rho_diff_vs_gpu": float(np.max(np.abs(got - np.asarray(want))))}}
 
 
 def _timed(ctx, torch, fn, reps, profile):
@@ -340,76 +397,155 @@ def elasticity_leg(ctx, torch, dev, stream, reps=3):
     return out
 
 
-def served_leg(ctx, n_jobs, load, seed=4):
-    """Served form on the job-stream workload: capacity from a closed loop
-    (all jobs submitted at once), then an open loop of Poisson arrivals at
-    `load` x capacity for p50/p99 latency.  Comparisons: the same jobs one
-    after another through ccm() (each call batched), the first few through
-    ccm() with one launch per realization (the unbatched form), and the
-    closed loop again with distance indexing tables (same results)."""
-    stream = synth.job_stream(n_jobs, 1.0, seed=seed)
-    jobs = []
-    for j in stream:
-        X, Y = j["make"]()
-        jobs.append((X, Y, j))
+def _serve(srv, jobs, arrivals, flags=0):
+    """Submit jobs at the given arrival times (seconds from now), wait for all;
+    returns (makespan, latencies submit->done, stats of each job)."""
+    t0 = time.perf_counter()
+    tickets = []
+    for (X, Y, j), ta in zip(jobs, arrivals):
+        delay = ta - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append((srv.submit(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"],
+                                   flags=flags), j))
+    lat, stats = [], []
+    for t, j in tickets:
+        assert srv.wait(t) == capi.CCM_OK
+        _, _, st = srv.result(t, len(j["L"]), j["r"])
+        lat.append(st["t_done"] - st["t_submit"])
+        stats.append(st)
+    return time.perf_counter() - t0, np.asarray(lat), stats
 
-    def run(srv, arrivals, flags=0):
-        t0 = time.perf_counter()
-        tickets = []
-        for (X, Y, j), ta in zip(jobs, arrivals):
-            delay = ta - (time.perf_counter() - t0)
-            if delay > 0:
-                time.sleep(delay)
-            tickets.append((srv.submit(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"],
-                                       flags=flags), j))
-        lat, preds = [], 0.0
-        for t, j in tickets:
-            assert srv.wait(t) == capi.CCM_OK
-            _, _, st = srv.result(t, len(j["L"]), j["r"])
-            lat.append(st["t_done"] - st["t_submit"])
-            preds += st["predictions"]
-        return time.perf_counter() - t0, np.asarray(lat), preds
 
+def _max_concurrent(stats):
+    ev = sorted([(s["t_admit"], 1) for s in stats] + [(s["t_done"], -1) for s in stats])
+    cur = best = 0
+    for _, d in ev:
+        cur += d
+        best = max(best, cur)
+    return best
+
+
+def load_points(ctx, jobs, capacity, loads, seed, discard):
+    """Open loops of Poisson arrivals at each load x capacity: p50/p99 job
+    latency (submit to result) over the jobs after the first `discard`."""
+    pts = []
     with capi.Server(ctx) as srv:
-        run(srv, [0.0] * min(4, n_jobs))                      # warm the server up
-        make_closed, lat_closed, preds = run(srv, [0.0] * n_jobs)
-        capacity = n_jobs / make_closed
-        rate = load * capacity
-        gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n_jobs)
-        arrivals = np.cumsum(gaps) - gaps[0]
-        make_open, lat_open, _ = run(srv, list(arrivals))
-        make_tables, _, _ = run(srv, [0.0] * n_jobs, flags=capi.CCM_FLAG_TABLE)
+        _serve(srv, jobs[:4], [0.0] * 4)                 # warm the server up
+        for k, load in enumerate(loads):
+            rate = load * capacity
+            gaps = np.random.default_rng([seed, 17, k]).exponential(1.0 / rate, len(jobs))
+            arrivals = np.cumsum(gaps) - gaps[0]
+            make, lat, _ = _serve(srv, jobs, list(arrivals))
+            kept = lat[discard:]
+            pts.append({"load": load, "arrival_rate_jobs_per_sec": rate, "jobs": len(jobs),
+                        "discarded": discard, "throughput_jobs_per_sec": len(jobs) / make,
+                        "p50_latency_ms": float(np.percentile(kept, 50) * 1e3),
+                        "p99_latency_ms": float(np.percentile(kept, 99) * 1e3),
+                        "mean_latency_ms": float(kept.mean() * 1e3)})
+            print(f"bench: served load {load}: p50 {pts[-1]['p50_latency_ms']:.0f} ms, "
+                  f"p99 {pts[-1]['p99_latency_ms']:.0f} ms", file=sys.stderr, flush=True)
+    return pts
+
+
+def served_leg(ctx, n_jobs, loads, n_cap=100, seed=4):
+    """Served form on the job-stream workload (jobs of coupled-logistic pairs,
+    N ~ U[1000, 50000], E ~ U[1, 10], tau ~ U[1, 4], 10-point L grid,
+    r = 100, both directions).
+      capacity: the first n_cap jobs submitted at once (closed loop), against
+        the same jobs one after another through ccm() (each call batched) and
+        the first three through ccm() with one launch per realization;
+      load points: Poisson arrivals of n_jobs jobs at each load x capacity,
+        p50/p99 latency over the jobs after the first 5%;
+      budget: the closed loop again under an HBM budget of twice the largest
+        job's footprint, so admission binds;
+      tables: the closed loop with distance indexing tables (same results)."""
+    stream = synth.job_stream(max(n_jobs, n_cap), 1.0, seed=seed)
+    jobs = [(*j["make"](), j) for j in stream]
+    cap_jobs = jobs[:n_cap]
+    with capi.Server(ctx) as srv:
+        _serve(srv, jobs[:4], [0.0] * 4)                 # warm the server up
+        make_closed, _, stats = _serve(srv, cap_jobs, [0.0] * len(cap_jobs))
+        make_tables, _, _ = _serve(srv, cap_jobs, [0.0] * len(cap_jobs),
+                                   flags=capi.CCM_FLAG_TABLE)
+    capacity = len(cap_jobs) / make_closed
+    preds = sum(st["predictions"] for st in stats)
+    foot = max(st["device_bytes"] for st in stats)
+    with capi.Server(ctx, hbm_budget_bytes=2 * foot) as srv:
+        make_budget, _, stats_b = _serve(srv, cap_jobs, [0.0] * len(cap_jobs))
     per_job = []
-    for X, Y, j in jobs:
+    for X, Y, j in cap_jobs:
         t0 = time.perf_counter()
         ctx.ccm(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"])
         per_job.append(time.perf_counter() - t0)
     fifo = sum(per_job)
-    n_plain = min(3, n_jobs)
+    n_plain = 3
     t0 = time.perf_counter()
-    for X, Y, j in jobs[:n_plain]:
+    for X, Y, j in cap_jobs[:n_plain]:
         ctx.ccm(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"], flags=capi.CCM_FLAG_PLAIN)
     fifo_plain = time.perf_counter() - t0
+    points = load_points(ctx, jobs[:n_jobs], capacity, loads, seed, max(1, n_jobs // 20))
     return {
-        "workload": f"{n_jobs} jobs: coupled-logistic pairs, N~U[1000,50000], E~U[1,10], "
-                    "tau~U[1,4], 10-point geometric L grid, r=100",
+        "workload": f"job stream (seed {seed}): coupled-logistic pairs, N~U[1000,50000], "
+                    "E~U[1,10], tau~U[1,4], 10-point geometric L grid, r=100",
+        "capacity_jobs": len(cap_jobs),
         "capacity_jobs_per_sec": capacity,
         "closed_loop_predictions_per_sec": preds / make_closed,
-        "arrival_rate_jobs_per_sec": rate,
-        "load": load,
-        "p50_latency_ms": float(np.percentile(lat_open, 50) * 1e3),
-        "p99_latency_ms": float(np.percentile(lat_open, 99) * 1e3),
-        "mean_latency_ms": float(lat_open.mean() * 1e3),
-        "open_loop_jobs_per_sec": n_jobs / make_open,
-        "fifo_ccm_jobs_per_sec": n_jobs / fifo,
-        "served_over_fifo": (n_jobs / make_closed) / (n_jobs / fifo),
-        "capacity_jobs_per_sec_with_tables": n_jobs / make_tables,
+        "fifo_ccm_jobs_per_sec": len(cap_jobs) / fifo,
+        "served_over_fifo": capacity / (len(cap_jobs) / fifo),
+        "load_points": points,
+        "budget": {"hbm_budget_bytes": 2 * foot, "largest_job_bytes": foot,
+                   "jobs_per_sec": len(cap_jobs) / make_budget,
+                   "max_jobs_on_device": _max_concurrent(stats_b),
+                   "max_jobs_on_device_unbounded": _max_concurrent(stats)},
+        "capacity_jobs_per_sec_with_tables": len(cap_jobs) / make_tables,
         "tables_over_scan": make_closed / make_tables,
         "plain_subset_jobs": n_plain,
         "plain_subset_seconds": fifo_plain,
         "batched_subset_seconds": sum(per_job[:n_plain]),
         "batched_over_plain": fifo_plain / sum(per_job[:n_plain]),
     }
+
+
+def serve_protocol(ctx, n_jobs=1000, loads=(0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 0.95), seed=4,
+                   n_cap=100):
+    """The served form's full protocol: capacity from a closed loop of n_cap
+    jobs, then n_jobs Poisson arrivals at each load x capacity, the first 50
+    jobs of each point discarded."""
+    stream = synth.job_stream(n_jobs, 1.0, seed=seed)
+    jobs = [(*j["make"](), j) for j in stream]
+    with capi.Server(ctx) as srv:
+        _serve(srv, jobs[:4], [0.0] * 4)
+        make, _, _ = _serve(srv, jobs[:n_cap], [0.0] * n_cap)
+    capacity = n_cap / make
+    return {"capacity_jobs_per_sec": capacity, "capacity_jobs": n_cap,
+            "load_points": load_points(ctx, jobs, capacity, list(loads), seed, 50)}
+
+
+def forms_leg(ctx, torch, dev, stream, default_ms, reps=2):
+    """The sweep's launch forms on the same GPU: the default (one launch per
+    E and wave, replayed from a HIP graph) against a persistent grid per
+    launch and against direct launches without the graph; and the batched
+    form against one launch per realization on the sweep's r = 1 subset
+    (2000 realizations, 10 ms batched)."""
+    f64 = dict(dtype=torch.float64, device=dev)
+    w = synth.workload_sweep()
+    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+    rho = torch.empty((2, len(w.E), len(w.tau), len(w.L), w.r), **f64)
+
+    def sweep(flags, r=w.r, out=rho):
+        return lambda: ctx.ccm_sweep_dev(X, Y, w.E, w.tau, w.L, r, w.seed, out, stream=stream,
+                                         flags=flags)
+    pers, _ = _timed(ctx, torch, sweep(capi.CCM_FLAG_PERSISTENT), reps, False)
+    nog, _ = _timed(ctx, torch, sweep(capi.CCM_FLAG_NO_GRAPH), reps, False)
+    rho1 = torch.empty((2, len(w.E), len(w.tau), len(w.L), 1), **f64)
+    b1, _ = _timed(ctx, torch, sweep(0, 1, rho1), 3, False)
+    p1, _ = _timed(ctx, torch, sweep(capi.CCM_FLAG_PLAIN, 1, rho1), 1, False)
+    return {"workload": w.name,
+            "default_ms": default_ms, "persistent_ms": pers * 1e3, "no_graph_ms": nog * 1e3,
+            "persistent_over_default": pers * 1e3 / default_ms,
+            "plain_vs_batched": {"subset": "r = 1 (2000 realizations)", "batched_ms": b1 * 1e3,
+                                 "plain_ms": p1 * 1e3, "plain_over_batched": p1 / b1}}
 
 
 def main():
@@ -429,27 +565,46 @@ def main():
                       device=dev)
     stream = torch.cuda.current_stream()
     ctx = capi.Context(0)
+    if a.serve_protocol:
+        print(json.dumps({"served_protocol": serve_protocol(ctx)}), flush=True)
+        ctx.close()
+        return
 
     def step():
         ctx.ccm_sweep_dev(X, Y, w.E, w.tau, w.L, w.r, w.seed, rho, stream=stream,
                           flags=a.flags)
 
-    ctx.profile_enable(True)
+    ctx.profile_enable(False)
     print(f"bench: warmup {a.warmup} step(s) of {w.name}", file=sys.stderr, flush=True)
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.profile_read(reset=True)
 
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile_read(reset=True)
     el = t1 - t0
-    print(f"bench: {a.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
+    print(f"bench: {a.steps} steps in {el:.3f} s (graph replay)", file=sys.stderr, flush=True)
+
+    # the same steps with every cross-map launch timed by HIP events
+    n_prof = max(1, min(a.steps, 5))
+    ctx.profile_enable(True)
+    step()
+    torch.cuda.synchronize()
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for i in range(n_prof):
+        step()
+    torch.cuda.synchronize()
+    el_prof = time.perf_counter() - t0
+    prof = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    for k in ("kernel_ms", "launches", "pairs", "flops", "predictions", "realizations",
+              "waves"):
+        prof[k] = prof[k] / n_prof * a.steps          # per timed region of a.steps steps
+    print(f"bench: {n_prof} profiled steps in {el_prof:.3f} s", file=sys.stderr, flush=True)
 
     if a.copy_mib > 0:
         n = a.copy_mib * (1 << 20) // 4
@@ -500,6 +655,10 @@ def main():
             "avg_launch_ms": prof["kernel_ms"] / launches,
             "kernel_share_of_step": kernel_s / el,
             "pairs_per_step": prof["pairs"] / a.steps,
+            "waves_per_step": prof["waves"] / a.steps,
+            "kernel_timing": f"HIP events around each cross-map launch, {n_prof} profiled "
+                             "steps (direct launches) after the timed graph steps",
+            "profiled_ms_per_step": el_prof / n_prof * 1e3,
         },
     }
     if a.workloads:
@@ -509,13 +668,15 @@ def main():
         out["index_table"] = table_leg(ctx, torch, dev, stream)
         out["nested"] = nested_leg(ctx, torch, dev, stream)
         out["shared_e"] = shared_e_leg(ctx, torch, dev, stream, out["ms_per_step"])
+        out["forms"] = forms_leg(ctx, torch, dev, stream, out["ms_per_step"])
     if a.serve_jobs > 0:
-        print(f"bench: served leg, {a.serve_jobs} jobs", file=sys.stderr, flush=True)
+        print(f"bench: served leg, {a.serve_jobs} jobs per load", file=sys.stderr, flush=True)
         ctx.profile_enable(False)
-        out["served"] = served_leg(ctx, a.serve_jobs, a.serve_load)
-    if a.cpu_seconds > 0:
-        print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+        loads = [float(v) for v in a.serve_loads.split(",") if v]
+        out["served"] = served_leg(ctx, a.serve_jobs, loads)
+    if a.cpu_modulus > 0:
+        print("bench: timing the CPU oracle on its sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, rh, modulus=a.cpu_modulus)
     ctx.close()
     print(json.dumps(out), flush=True)
 

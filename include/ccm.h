@@ -359,7 +359,8 @@ ccm_status ccm_neighbors(ccm_ctx *ctx, const double *lib_series,
                          double *pred, double *rho);
 
 /* Kernel timing of the cross-map kernels (HIP events on the launch stream).
-   While enabled, batched calls issue their launches directly (no graph). */
+   While enabled, batched calls issue their launches directly (no graph: the
+   runtime cannot time events recorded by graph nodes). */
 typedef struct {
   double kernel_ms;      /* summed duration of cross-map kernel launches */
   int64_t launches;      /* cross-map kernel launches timed */

@@ -255,6 +255,28 @@ class Oracle:
                                 parts))
         return self.pearson(T[off:off + Ne], np.concatenate(preds))
 
+    def deterministic_sample(self, X, Y, Es, taus, Ls, r, seed, modulus):
+        """The realizations of a sweep whose library stream state (the fold of
+        (seed, E, tau, L_eff, r_index) that keys the draw) is 0 mod
+        ``modulus``, both directions of each: a fixed sample for timing the
+        oracle and checking the GPU.  Returns (tasks, picks): ``realization``
+        argument tuples and their (direction, iE, itau, iL, r_index) indices
+        in the sweep's rho."""
+        N = len(X)
+        tasks, picks = [], []
+        for ie, e in enumerate(Es):
+            for it, t in enumerate(taus):
+                ne = N - (e - 1) * t
+                for il, l in enumerate(Ls):
+                    le = min(int(l), ne)
+                    for ri in range(r):
+                        if self.library_state(seed, e, t, le, ri) % modulus:
+                            continue
+                        for d, (S, T) in enumerate(((Y, X), (X, Y))):
+                            tasks.append((S, T, e, t, l, ri, seed, 0, 0))
+                            picks.append((d, ie, it, il, ri))
+        return tasks, picks
+
     def realizations_threaded(self, tasks, threads=None):
         """rho of many realizations; ``tasks`` holds ``realization`` argument tuples."""
         threads = threads or default_threads()

@@ -86,9 +86,11 @@ namespace ccmh {
 
 // Queue every launch of plan p on stream st (buffers b; plain_first: each
 // realization's first item in b.plain_items, for CCM_FLAG_PLAIN).  With
-// `timed`, each cross-map launch is bracketed by HIP events of the context.
+// evs set, each cross-map launch is bracketed by a pair of HIP events
+// (taken from the context's pool), appended to *evs.
 void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
-                  const std::vector<int64_t>& plain_first, hipStream_t st, bool timed);
+                  const std::vector<int64_t>& plain_first, hipStream_t st,
+                  std::vector<EvPair>* evs);
 
 // The static workspace of the no-allocation entry point on the current
 // device: set up once per device (at context creation); false, with a

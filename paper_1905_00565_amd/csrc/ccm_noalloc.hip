@@ -118,7 +118,7 @@ extern "C" ccm_status ccm_dev_noalloc(ccm_ctx* c, const double* X, const double*
     put(b.segoff, p.seg_off.data(), p.seg_off.size() * 4);
     HIPCHK(hipMemcpyAsync(b.s64, X, N * 8, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(b.s64 + N, Y, N * 8, hipMemcpyDeviceToDevice, st));
-    enqueue_plan(c, p, b, {}, st, false);
+    enqueue_plan(c, p, b, {}, st, nullptr);
     const int64_t half = (int64_t)nL * r;
     HIPCHK(hipMemcpyAsync(rho_xy, b.out, half * 8, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(rho_yx, b.out + half, half * 8, hipMemcpyDeviceToDevice, st));

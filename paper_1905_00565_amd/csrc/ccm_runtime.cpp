@@ -152,9 +152,10 @@ int persistent_grid(ccm_ctx* c, int n_items) {
 // One cross-map launch over items [first, first + n) of b.items (or of
 // b.plain_items), E's kernel variant for the plan's form.
 void launch_items(ccm_ctx* c, const Plan& p, const PlanBuffers& b, const Item* items, int n,
-                  int E, int grid, int* next, int table_ne, hipStream_t st, bool timed) {
+                  int E, int grid, int* next, int table_ne, hipStream_t st,
+                  std::vector<EvPair>* evs) {
   EvPair ev;
-  if (timed) {
+  if (evs) {
     ev = take_events(c);
     HIPCHK(hipEventRecord(ev.a, st));
   }
@@ -175,9 +176,9 @@ void launch_items(ccm_ctx* c, const Plan& p, const PlanBuffers& b, const Item* i
     HIPCHK(launch_crossmap(E, p.mode, grid, b.rz, items, n, next, b.emb, b.pts, b.pj, b.qord,
                            b.start, b.s64, static_cast<Moments*>(b.partial), p.spec.query_set,
                            p.window, nodump, b.table, table_ne, st));
-  if (timed) {
+  if (evs) {
     HIPCHK(hipEventRecord(ev.b, st));
-    c->ev_pending.push_back(ev);
+    evs->push_back(ev);
   }
 }
 
@@ -186,7 +187,8 @@ void launch_items(ccm_ctx* c, const Plan& p, const PlanBuffers& b, const Item* i
 namespace ccmh {
 
 void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
-                  const std::vector<int64_t>& plain_first, hipStream_t st, bool timed) {
+                  const std::vector<int64_t>& plain_first, hipStream_t st,
+                  std::vector<EvPair>* evs) {
   HIPCHK(launch_ingest(b.ingest, (int)p.ingest.size(), p.n64, b.s64, b.s32, st));
   HIPCHK(launch_embed(b.embed, (int)p.embed.size(), p.max_embed, b.s32, b.emb, st));
   if (p.spec.M > 0) HIPCHK(launch_transpose_targets(b.s64, p.spec.M, p.spec.N, b.tt, st));
@@ -226,7 +228,7 @@ void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
           HIPCHK(launch_zero_int(next, 1, st));
         }
         launch_items(c, p, b, b.items + L.first, L.count, L.E, grid, next, p.e_table_ne[L.E],
-                     st, timed);
+                     st, evs);
       }
     } else {
       // the unbatched baseline: sampler, gather and cross-map launched per
@@ -244,7 +246,7 @@ void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
         HIPCHK(launch_gather(b.gather + p.rz_gather[r], 1, G.sorted ? G.n_e : 0, b.emb, b.lib,
                              b.order, b.pts, b.pj, b.start, st));
         launch_items(c, p, b, b.plain_items + plain_first[r], R.n_tiles, R.E, R.n_tiles,
-                     nullptr, R.table_off >= 0 ? R.n_e : 0, st, timed);
+                     nullptr, R.table_off >= 0 ? R.n_e : 0, st, evs);
       }
     }
   }
@@ -263,33 +265,41 @@ void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
 
 namespace {
 
-// Run a prepared plan on stream st: series already in ex->d_s64.
+// Capture the plan's launches into an executable graph.
+hipGraphExec_t capture(ccm_ctx* c, Exec* ex) {
+  hipStream_t cap = c->stream;
+  HIPCHK(hipStreamSynchronize(cap));
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue_plan(c, ex->plan, ex->buf, ex->plain_first, cap, nullptr);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamEndCapture(cap, &g));
+  hipGraphExec_t gx = nullptr;
+  hipError_t e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(e);
+  return gx;
+}
+
+// Run a prepared plan on stream st: series already in ex->d_s64.  While
+// profiling, the launches are issued directly with an event pair around
+// each cross-map launch (events recorded by graph nodes cannot be timed).
 void run(ccm_ctx* c, Exec* ex, hipStream_t st) {
   const Plan& p = ex->plan;
   const bool use_graph = !c->profiling && !(p.spec.flags & CCM_FLAG_NO_GRAPH) &&
                          !(p.spec.flags & CCM_FLAG_PLAIN);
   if (use_graph) {
-    if (!ex->graph) {
-      hipStream_t cap = c->stream;
-      HIPCHK(hipStreamSynchronize(cap));
-      HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-      try {
-        enqueue_plan(c, ex->plan, ex->buf, ex->plain_first, cap, false);
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(cap, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
-      hipGraph_t g = nullptr;
-      HIPCHK(hipStreamEndCapture(cap, &g));
-      hipError_t e = hipGraphInstantiate(&ex->graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      HIPCHK(e);
-    }
+    if (!ex->graph) ex->graph = capture(c, ex);
     HIPCHK(hipGraphLaunch(ex->graph, st));
   } else {
-    enqueue_plan(c, ex->plan, ex->buf, ex->plain_first, st, c->profiling);
+    enqueue_plan(c, ex->plan, ex->buf, ex->plain_first, st,
+                 c->profiling ? &c->ev_pending : nullptr);
   }
   if (c->profiling) {
     c->prof.waves += (double)p.waves.size();

@@ -163,3 +163,12 @@ def test_matrix_every_L(ctx, orc):
     h = hook_vs_oracle(ctx, orc, S[7], S[30], m["E"], m["tau"], lib, 256,
                        np.random.default_rng(6))
     assert abs(h - rho[7, 30, len(m["L"]) - 2, 9]) < 1e-12
+
+
+def test_sweep_deterministic_sample_vs_oracle(orc, sweep):
+    """The sample the bench times the oracle on (realizations whose library
+    stream state is 0 mod 1000, both directions) against the sweep's rho."""
+    w, rho = sweep
+    tasks, picks = orc.deterministic_sample(w.X, w.Y, w.E, w.tau, w.L, w.r, w.seed, 1000)
+    assert len(tasks) > 400
+    close([rho[p] for p in picks], orc.realizations_threaded(tasks))

@@ -211,3 +211,21 @@ def test_invalid_inputs(ctx):
     # clamping is not an error
     _, _, le = ctx.ccm(x, y, 2, 1, [10**6], 1, 1)
     assert le.tolist() == [49]
+
+
+def test_profiled_launches(ctx):
+    """While profiling, every cross-map launch is timed (direct launches);
+    results equal the graph path's, bit for bit."""
+    x, y = synth.coupled_logistic(3000)
+    args = (x, y, [2, 7], [1, 3], [100, 3000], 6, 21)
+    ref = ctx.ccm_sweep(*args)
+    ctx.profile_enable(True)
+    ctx.profile_read(reset=True)
+    a = ctx.ccm_sweep(*args)
+    b = ctx.ccm_sweep(*args, flags=capi.CCM_FLAG_PERSISTENT)
+    p = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    for got in (a, b):
+        assert np.array_equal(ref, got, equal_nan=True)
+    assert p["launches"] == 4 and p["waves"] == 2        # one launch per E, per call
+    assert p["kernel_ms"] > 0 and p["realizations"] == 2 * ref.size

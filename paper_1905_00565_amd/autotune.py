@@ -87,24 +87,22 @@ def _brace(v):
 
 
 def _build_column(k, q, g, w, kind="default"):
-    obj = os.path.join(TUNE_DIR, f"kernels_{k}.o")
     mq, mg, mw = MACROS[kind]
-    cmd = [B.hipcc(), *B.common_flags(), f"-D{mq}={_brace(q)}", f"-D{mg}={_brace(g)}",
-           f"-D{mw}={_brace(w)}",
-           "-c", os.path.join(B.CSRC, "ccm_kernels.hip"), "-o", obj]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed on column {k}")
-    others = [os.path.join(B.BUILD, os.path.splitext(s)[0] + ".o")
-              for s in B.SOURCES if s != "ccm_kernels.hip"]
+    defines = [f"-D{mq}={_brace(q)}", f"-D{mg}={_brace(g)}", f"-D{mw}={_brace(w)}"]
+    col = os.path.join(TUNE_DIR, f"col{k}")
+    os.makedirs(col, exist_ok=True)
+    objs = []
+    for src, obj, extra in B.units(defines):
+        if extra:                       # a unit that holds kernels: rebuild it
+            obj = os.path.join(col, os.path.basename(obj))
+            B.compile_unit(src, obj, extra)
+        objs.append(obj)
     lib = os.path.join(TUNE_DIR, f"libccm_{k}.so")
     res = subprocess.run([B.hipcc(), f"--offload-arch={B.ARCH}", "-shared", "-fPIC", "-o", lib,
-                          obj, *others], capture_output=True, text=True)
+                          *objs], capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError(f"link failed on column {k}")
-    os.remove(obj)
     return lib
 
 

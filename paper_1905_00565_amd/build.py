@@ -25,6 +25,10 @@ LIBRARY = os.path.join(PKG, "libccm.so")
 ARCH = os.environ.get("CCM_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["ccm_kernels.hip", "ccm_sort.hip", "ccm_noalloc.hip", "ccm_plan.cpp",
            "ccm_runtime.cpp", "ccm_server.cpp"]
+# ccm_inst.hip is compiled once per embedding dimension (its kernels are the
+# bulk of the build, so the ten compile in parallel).
+INST_SOURCE = "ccm_inst.hip"
+INST_E = tuple(range(1, 11))
 
 
 def hipcc() -> str:
@@ -42,20 +46,39 @@ def common_flags():
             "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+def units(defines=()):
+    """(source, object, extra flags) of every translation unit; ``defines``
+    go to the units that hold kernels (the tuner's shape tables)."""
+    out = []
+    for src in SOURCES:
+        extra = list(defines) if src == "ccm_kernels.hip" else []
+        out.append((src, os.path.join(BUILD, os.path.splitext(src)[0] + ".o"), extra))
+    for e in INST_E:
+        out.append((INST_SOURCE, os.path.join(BUILD, f"ccm_inst_e{e}.o"),
+                    [f"-DCCM_INST_E={e}", *defines]))
+    return out
+
+
+def compile_unit(src: str, obj: str, extra=()) -> str:
+    cmd = [hipcc(), *common_flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed on {src}")
+        raise RuntimeError(f"hipcc failed on {src} {' '.join(extra)}")
     return obj
+
+
+def jobs() -> int:
+    return max(1, min(16, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
 
 
 def build_library(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    # the per-E units first, largest E first, so the long compiles start at once
+    todo = units()
+    todo = todo[len(SOURCES):][::-1] + todo[:len(SOURCES)]
+    with ThreadPoolExecutor(max_workers=jobs()) as ex:
+        objs = list(ex.map(lambda u: compile_unit(*u), todo))
     tmp = LIBRARY + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)

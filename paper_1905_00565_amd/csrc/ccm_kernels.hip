@@ -27,13 +27,17 @@
 //   k ascending from acc = +0 (the first term is the plain product, which is
 //   the same value), no other contraction (-ffp-contract=off);
 //   neighbours are the first E+1 candidates in (d2, j) order.
+// The cross-map kernels themselves are templates in ccm_device.h, compiled
+// once per E by ccm_inst.hip; this file holds the kernels that do not depend
+// on E and the launchers that dispatch by E.
+//
 // The order in which candidates are visited is free: selection uses the exact
 // (d2, j) key.  Queries are grouped and candidates visited roughly nearest
 // first (along a space-filling curve) only so that the running lists settle
 // early and the insertion path stays rare; every (query, candidate) pair is
 // still evaluated.
-#include "ccm_internal.h"
-#include "ccm_tune.h"
+#include "ccm_device.h"
+#include "ccm_inst.h"
 
 namespace ccmk {
 
@@ -181,28 +185,6 @@ __global__ __launch_bounds__(256) void k_order_keys(const OrderJob* __restrict__
       x[d] = (uint32_t)fminf(top, fmaxf(0.f, (s[i + J.lag[d]] - lo) * scale));
     k[i] = dims == 2 ? hilbert16(x[0], x[1]) : hilbert_nd(x, dims, bits);
   }
-}
-
-// Exclusive rank of this thread among the flagged threads of its 256-thread
-// workgroup, and the workgroup total, in thread order.
-__device__ __forceinline__ int block_rank(bool flag, int* s_wave, int& total) {
-  const uint64_t m = __builtin_amdgcn_ballot_w64(flag);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int r = __popcll(m & lt);
-  if (lane == 0) s_wave[wave] = __popcll(m);
-  __syncthreads();
-  int before = 0;
-  total = 0;
-#pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
-    const int c = s_wave[w];
-    if (w < wave) before += c;
-    total += c;
-  }
-  __syncthreads();
-  return before + r;
 }
 
 // Embedded points in visiting order: the order set restricted to indices
@@ -378,1219 +360,6 @@ __global__ __launch_bounds__(kBlock) void k_gather(
   }
 }
 
-// ---------------------------------------------------------------------------
-// candidate keys
-// ---------------------------------------------------------------------------
-//
-// A candidate (d2, j) is kept as one 64-bit word: high half the binary32 bits
-// of d2, low half its embedded index j.  For d2 >= 0 the bit patterns of
-// binary32 order like the values, so the word read as an unsigned integer
-// orders exactly like (d2, j) lexicographically.  The same word read as a
-// binary64 is a non-negative number (denormal when d2 is 0 or tiny, never
-// NaN: the high
-// exponent field is at most 0x7f8), and non-negative binary64 values also
-// order like their bit patterns -- so the FP64 min/max units keep a sorted
-// list of keys, two instructions per slot.  FP64 denormals are preserved in
-// the kernel's float mode, which this relies on.
-
-__device__ __forceinline__ double make_key(float d2, int32_t j) {
-  return __hiloint2double(__float_as_int(d2), j);
-}
-__device__ __forceinline__ float key_d2(double k) {
-  return __int_as_float(__double2hiint(k));
-}
-__device__ __forceinline__ int32_t key_j(double k) { return __double2loint(k); }
-
-// Issued directly so the compiler does not quiet-NaN-canonicalise operands
-// that can never be NaN (see above).
-__device__ __forceinline__ double kmax(double a, double b) {
-  double r;
-  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-__device__ __forceinline__ double kmin(double a, double b) {
-  double r;
-  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-
-// Insert c into the ascending list key[0..KS-1], dropping the largest.
-// New slot m is the median of (old m-1, c, old m).  A c above the last key
-// leaves the list unchanged.
-template <int KS>
-__device__ __forceinline__ void insert_key(double (&key)[KS], double c) {
-#pragma unroll
-  for (int m = KS - 1; m >= 1; --m) key[m] = kmin(kmax(key[m - 1], c), key[m]);
-  key[0] = kmin(key[0], c);
-}
-
-// Empty slot: +inf distance, index above any real one.
-__device__ __forceinline__ double empty_key() {
-  return __hiloint2double(0x7f800000, -1);
-}
-
-template <int E>
-__device__ __forceinline__ float sqdist(const float (&q)[E], const float* p) {
-  float d = q[0] - p[0];
-  float acc = d * d;
-#pragma unroll
-  for (int k = 1; k < E; ++k) {
-    d = q[k] - p[k];
-    acc = __builtin_fmaf(d, d, acc);
-  }
-  return acc;
-}
-
-// ---------------------------------------------------------------------------
-// Pearson moments (Welford / Chan)
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void mom_add(Moments& a, double t, double p) {
-  a.n += 1.0;
-  const double dt = t - a.mt;
-  const double dp = p - a.mp;
-  a.mt += dt / a.n;
-  a.mp += dp / a.n;
-  a.m2t += dt * (t - a.mt);
-  a.m2p += dp * (p - a.mp);
-  a.c += dt * (p - a.mp);
-}
-
-__device__ __forceinline__ Moments mom_merge(const Moments& a, const Moments& b) {
-  if (b.n == 0.0) return a;
-  if (a.n == 0.0) return b;
-  Moments r;
-  r.n = a.n + b.n;
-  const double dt = b.mt - a.mt;
-  const double dp = b.mp - a.mp;
-  const double f = a.n * b.n / r.n;
-  r.mt = a.mt + dt * (b.n / r.n);
-  r.mp = a.mp + dp * (b.n / r.n);
-  r.m2t = a.m2t + b.m2t + dt * dt * f;
-  r.m2p = a.m2p + b.m2p + dp * dp * f;
-  r.c = a.c + b.c + dt * dp * f;
-  return r;
-}
-
-// ---------------------------------------------------------------------------
-// the fused cross-map item
-// ---------------------------------------------------------------------------
-
-// Library candidates per trigger check (tuned per E); the group's
-// coordinates (G*E values, uniform across the wavefront) come through the
-// scalar cache into SGPRs.
-template <int E>
-struct Group {
-  static constexpr int G = kTuneG[E];
-};
-
-// Running list length: the E+1 neighbours.  With self excluded the query
-// itself is rejected when it would be inserted, so it never takes a slot.
-template <int E, int MODE>
-struct Slots {
-  static constexpr int KS = E + 1;
-};
-
-// G consecutive library candidates (uniform across the wavefront: loaded
-// through the scalar cache into SGPRs).
-template <int E, int G>
-struct Chunk {
-  float p[G][E];
-  int32_t j[G];
-};
-
-template <int E, int G>
-__device__ __forceinline__ void load_chunk(Chunk<E, G>& ch, const float* __restrict__ pts,
-                                           const int32_t* __restrict__ pj, int c) {
-  // one base address per chunk: the G*E coordinates and G indices are
-  // contiguous, so the loads merge into a few wide scalar loads with
-  // immediate offsets
-  const float* __restrict__ p = pts + (int64_t)c * E;
-  const int32_t* __restrict__ q = pj + c;
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-#pragma unroll
-    for (int k = 0; k < E; ++k) ch.p[g][k] = p[g * E + k];
-    ch.j[g] = q[g];
-  }
-}
-
-// Make the chunk's values available at this point (the wait for its scalar
-// loads happens here, before anything issued after it).
-template <int E, int G>
-__device__ __forceinline__ void settle_chunk(const Chunk<E, G>& ch) {
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-#pragma unroll
-    for (int k = 0; k < E; ++k) asm volatile("" ::"s"(ch.p[g][k]));
-    asm volatile("" ::"s"(ch.j[g]));
-  }
-}
-
-// Distances from the lane's queries to the chunk's candidates, then one
-// compare per query against its running (KS)-th best; only when some lane
-// of the wavefront qualifies are the candidates inserted.
-template <int E, int Q, int MODE, int G>
-__device__ __forceinline__ void compute_chunk(
-    const Chunk<E, G>& ch, const float (&qc)[Q][E], const int (&qi)[Q], int window,
-    double (&key)[Q][Slots<E, MODE>::KS]) {
-  constexpr int KS = Slots<E, MODE>::KS;
-  float d2[G][Q];
-#pragma unroll
-  for (int g = 0; g < G; ++g)
-#pragma unroll
-    for (int m = 0; m < Q; ++m) {
-      float v = sqdist<E>(qc[m], ch.p[g]);
-      if (MODE == kWindow) {
-        const int dj = ch.j[g] - qi[m];
-        if (dj <= window && dj >= -window) v = __builtin_nanf("");
-      }
-      d2[g][m] = v;
-    }
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    float mn = d2[0][m];
-#pragma unroll
-    for (int g = 1; g < G; ++g) mn = fminf(mn, d2[g][m]);
-    if (__builtin_amdgcn_ballot_w64(mn <= key_d2(key[m][KS - 1]))) {
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-        if (d2[g][m] <= key_d2(key[m][KS - 1]) && (MODE != kExclSelf || ch.j[g] != qi[m]))
-          insert_key<KS>(key[m], make_key(d2[g][m], ch.j[g]));
-    }
-  }
-}
-
-template <int E, int Q, int MODE, int G>
-__device__ __forceinline__ void scan_group(
-    const float* __restrict__ pts, const int32_t* __restrict__ pj, int c,
-    const float (&qc)[Q][E], const int (&qi)[Q], int window,
-    double (&key)[Q][Slots<E, MODE>::KS]) {
-  Chunk<E, G> ch;
-  load_chunk<E, G>(ch, pts, pj, c);
-  compute_chunk<E, Q, MODE, G>(ch, qc, qi, window, key);
-}
-
-// Queries of one item and their running candidate lists after the scan of
-// the whole library.
-template <int E, int Q, int MODE>
-struct ScanState {
-  float qc[Q][E];
-  int qi[Q];
-  double key[Q][Slots<E, MODE>::KS];
-};
-
-// ---------------------------------------------------------------------------
-// distance indexing table (Section 3.2)
-// ---------------------------------------------------------------------------
-//
-// The walk of a query's table row: the first E+1 library members that are
-// not excluded, in the row's (d2, j) order, are exactly the E+1 neighbours
-// the brute-force scan selects (every candidate before them in the row is
-// either outside the library or excluded, and every candidate after them is
-// larger in (d2, j)).  Their keys are recomputed from the coordinates with
-// the same binary32 chain, so the running lists end identical.  The library
-// is a membership bitmask in LDS (built per item), the accepted indices go to
-// a per-lane LDS slot array.  Returns false when some lane of the wavefront
-// reached the end of a row short of E+1 members (the caller then scans).
-
-struct TableArgs {
-  const int32_t* pool;  // int32 rows of every table
-  int32_t words;        // bitmask words in dynamic LDS (0: no table in this launch)
-  int32_t pad;
-};
-
-__device__ __forceinline__ int table_stride(int w) { return (w + 3) & ~3; }
-
-template <int E, int Q, int MODE>
-__device__ __forceinline__ bool walk_table(const Realization& R, const int32_t* __restrict__ table,
-                                           const uint32_t* __restrict__ bits,
-                                           int32_t* __restrict__ acc,
-                                           const float* __restrict__ emb, int window,
-                                           ScanState<E, Q, MODE>& S) {
-  constexpr int K = E + 1;
-  const int rs = table_stride(R.table_w);
-  bool ok = true;
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    const int qi = S.qi[m];
-    int cnt = qi >= 0 ? 0 : K;
-    if (qi >= 0) {
-      const int4* __restrict__ row =
-          reinterpret_cast<const int4*>(table + R.table_off + (int64_t)qi * rs);
-      for (int p = 0; p < rs / 4 && cnt < K; ++p) {
-        const int4 v = row[p];
-        const int js[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int j = js[u];
-          bool keep = cnt < K && j >= 0 && ((bits[j >> 5] >> (j & 31)) & 1u);
-          if (MODE == kExclSelf) keep = keep && j != qi;
-          if (MODE == kWindow) keep = keep && (j - qi > window || qi - j > window);
-          if (keep) {
-            acc[cnt * kBlock + threadIdx.x] = j;
-            ++cnt;
-          }
-        }
-      }
-      if (cnt == K) {
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-          const int j = acc[t * kBlock + threadIdx.x];
-          S.key[m][t] = make_key(sqdist<E>(S.qc[m], emb + (int64_t)j * E), j);
-        }
-      }
-    }
-    ok = ok && cnt == K;
-  }
-  return !__builtin_amdgcn_ballot_w64(!ok);
-}
-
-// Library membership bitmask of realization R in LDS (whole workgroup).
-__device__ __forceinline__ void table_bitmask(const Realization& R,
-                                              const int32_t* __restrict__ pj_pool,
-                                              uint32_t* bits) {
-  const int words = (R.n_e + 31) / 32;
-  for (int w = threadIdx.x; w < words; w += kBlock) bits[w] = 0u;
-  __syncthreads();
-  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
-  for (int c = threadIdx.x; c < R.l_eff; c += kBlock) {
-    const int j = pj[c];
-    atomicOr(&bits[j >> 5], 1u << (j & 31));
-  }
-  __syncthreads();
-}
-
-// Queries of this lane for item (R, tile): positions tile*QT + wave*QW +
-// m*64 + lane of the query order (every embedded point, or the ordered
-// library itself), so that each wavefront holds a run of QW consecutive
-// queries.  Their lists start empty.  Returns whether the lane's wavefront
-// has any query (uniform across the wavefront).
-template <int E, int Q, int MODE>
-__device__ __forceinline__ bool scan_queries(const Realization& R, int tile, int wave, int lane,
-                                             const float* __restrict__ emb,
-                                             const int32_t* __restrict__ pj,
-                                             const int32_t* __restrict__ qord, int query_set,
-                                             ScanState<E, Q, MODE>& S) {
-  constexpr int KS = Slots<E, MODE>::KS;
-  constexpr int QT = kBlock * Q;
-  constexpr int QW = 64 * Q;
-  bool any = false;
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    const int qq = tile * QT + wave * QW + m * 64 + lane;
-    const bool valid = qq < R.n_query;
-    any |= valid;
-    const int i = valid ? (query_set ? pj[qq] : qord[qq]) : 0;
-    S.qi[m] = valid ? i : -1;
-#pragma unroll
-    for (int k = 0; k < E; ++k) S.qc[m][k] = emb[(int64_t)i * E + k];
-  }
-#pragma unroll
-  for (int m = 0; m < Q; ++m)
-#pragma unroll
-    for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
-  return __builtin_amdgcn_ballot_w64(any) != 0;
-}
-
-// Brute-force scan of the library positions [0, L) (coordinates pts AoS,
-// indices pj), outward from s0: a forward group [f, f+G) and a backward
-// group [b-G, b) per step while both fit, then the remaining groups of the
-// longer side, then single positions at both ends.  Every position is
-// visited once; the lists keep the first E+1 candidates in (d2, j) order.
-template <int E, int Q, int MODE>
-__device__ __forceinline__ void scan_range(const float* __restrict__ pts,
-                                           const int32_t* __restrict__ pj, int L, int s0,
-                                           int window, ScanState<E, Q, MODE>& S) {
-  constexpr int G = Group<E>::G;
-  s0 = min(max(s0, 0), L);
-  int f = s0, b = s0;
-  const int both = min((L - s0) / G, s0 / G);
-  // Software pipeline over the scalar loads: a chunk's loads are issued one
-  // chunk ahead, and each chunk is waited for before the next is requested
-  // (scalar loads return out of order, so a wait covers all that are
-  // outstanding).
-  if (both > 0) {
-    Chunk<E, G> A, B;
-    load_chunk<E, G>(A, pts, pj, f);
-    for (int k = 0; k < both; ++k) {
-      settle_chunk<E, G>(A);
-      __builtin_amdgcn_sched_barrier(0);
-      load_chunk<E, G>(B, pts, pj, b - G);
-      __builtin_amdgcn_sched_barrier(0);
-      compute_chunk<E, Q, MODE, G>(A, S.qc, S.qi, window, S.key);
-      f += G;
-      settle_chunk<E, G>(B);
-      __builtin_amdgcn_sched_barrier(0);
-      load_chunk<E, G>(A, pts, pj, k + 1 < both ? f : f - G);
-      __builtin_amdgcn_sched_barrier(0);
-      compute_chunk<E, Q, MODE, G>(B, S.qc, S.qi, window, S.key);
-      b -= G;
-    }
-  }
-  for (; f + G <= L; f += G) scan_group<E, Q, MODE, G>(pts, pj, f, S.qc, S.qi, window, S.key);
-  for (; b - G >= 0; b -= G) scan_group<E, Q, MODE, G>(pts, pj, b - G, S.qc, S.qi, window, S.key);
-  for (; f < L; ++f) scan_group<E, Q, MODE, 1>(pts, pj, f, S.qc, S.qi, window, S.key);
-  for (; b > 0; --b) scan_group<E, Q, MODE, 1>(pts, pj, b - 1, S.qc, S.qi, window, S.key);
-}
-
-template <int E, int Q, int MODE, bool TBL>
-__device__ __forceinline__ void scan_library(
-    const Realization& R, int tile, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    int query_set, int window, const TableArgs& ta, uint32_t* tlds,
-    ScanState<E, Q, MODE>& S) {
-  constexpr int KS = Slots<E, MODE>::KS;
-  constexpr int QT = kBlock * Q;                    // queries per tile
-  constexpr int QW = 64 * Q;                        // queries per wavefront
-  // the wavefront index is uniform: say so, so that the scan position and
-  // the library addresses stay scalar
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const float* __restrict__ emb = emb_pool + R.emb_off;
-  const float* __restrict__ pts = pts_pool + R.pts_off;
-  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
-  const int32_t* __restrict__ qord = qord_pool + R.qord_off;
-  const int L = R.l_eff;
-
-  // A wavefront with no query (the tail of the last tile) has nothing to scan.
-  if (!scan_queries<E, Q, MODE>(R, tile, wave, lane, emb, pj, qord, query_set, S)) return;
-
-  // Table walk (the realization's rows exist): done unless a row ran short.
-  // Compiled only into the launches that carry tables.
-  if constexpr (TBL) {
-    if (R.table_off >= 0 && ta.words > 0) {
-      if (walk_table<E, Q, MODE>(R, ta.pool, tlds, reinterpret_cast<int32_t*>(tlds + ta.words),
-                                 emb, window, S))
-        return;
-#pragma unroll
-      for (int m = 0; m < Q; ++m)
-#pragma unroll
-        for (int s = 0; s < KS; ++s) S.key[m][s] = empty_key();
-    }
-  }
-
-  const int s0 = query_set ? min(tile * QT + wave * QW + QW / 2, L - 1)
-                           : start_pool[(R.slot_base + tile) * kWaves + wave];
-  scan_range<E, Q, MODE>(pts, pj, L, s0, window, S);
-}
-
-// The E+1 neighbours of query m (nearest first): its running list.  Every
-// slot holds a real candidate (the library has at least E+1 candidates
-// besides the excluded ones).
-template <int E, int Q, int MODE>
-__device__ __forceinline__ void select_neighbors(const ScanState<E, Q, MODE>& S, int m,
-                                                 float (&nd)[E + 1], int32_t (&nj)[E + 1]) {
-#pragma unroll
-  for (int t = 0; t < E + 1; ++t) {
-    nd[t] = key_d2(S.key[m][t]);
-    nj[t] = key_j(S.key[m][t]);
-  }
-}
-
-// Simplex-projection weights (Section 2.1): d = sqrt(d2) in double,
-// u = exp(-d / d_1) (or the zero-distance rule when d_1 = 0), w = u / sum u.
-template <int K>
-__device__ __forceinline__ void simplex_weights(const float (&nd)[K], double (&w)[K]) {
-  double dist[K], u[K];
-#pragma unroll
-  for (int t = 0; t < K; ++t) dist[t] = sqrt((double)nd[t]);
-  if (dist[0] > 0.0) {
-#pragma unroll
-    for (int t = 0; t < K; ++t) u[t] = exp(-dist[t] / dist[0]);
-  } else {
-#pragma unroll
-    for (int t = 0; t < K; ++t) u[t] = dist[t] == 0.0 ? 1.0 : 0.0;
-  }
-  double su = 0.0;
-#pragma unroll
-  for (int t = 0; t < K; ++t) su += u[t];
-#pragma unroll
-  for (int t = 0; t < K; ++t) w[t] = u[t] / su;
-}
-
-// DUMP (the test hook): every query's neighbours, squared distances and
-// prediction are written out as well.  The hook's instance has the batched
-// launches' Q, candidate groups, tiles and merge order; only the export
-// after the scan differs.
-template <int E, int Q, int MODE, bool DUMP, bool TBL>
-__device__ __forceinline__ void crossmap_item(
-    const Realization& R, int tile, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tgt_pool, Moments* __restrict__ partial,
-    int query_set, int window, const Dump& dump, Moments* red, const TableArgs& ta,
-    uint32_t* tlds) {
-  constexpr int K = E + 1;                          // neighbours (Section 3.2)
-  const int tid = threadIdx.x;
-  const double* __restrict__ tgt = tgt_pool + R.tgt_off;
-  const int64_t off = (int64_t)(E - 1) * R.tau;     // time of embedded point 0
-
-  if constexpr (TBL)
-    if (R.table_off >= 0 && ta.words > 0) table_bitmask(R, pj_pool, tlds);
-  ScanState<E, Q, MODE> S;
-  scan_library<E, Q, MODE, TBL>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
-                                query_set, window, ta, tlds, S);
-
-  // Simplex projection from the E+1 neighbours, then Pearson moments.
-  Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    if (S.qi[m] < 0) continue;
-    float nd[K];
-    int32_t nj[K];
-    select_neighbors<E, Q, MODE>(S, m, nd, nj);
-    double w[K];
-    simplex_weights<K>(nd, w);
-    double pred = 0.0;
-#pragma unroll
-    for (int t = 0; t < K; ++t) pred += w[t] * tgt[nj[t] + off];
-    mom_add(mo, tgt[S.qi[m] + off], pred);
-    if (DUMP) {
-      const int64_t row = S.qi[m];
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        dump.nbr[row * K + t] = nj[t];
-        dump.d2[row * K + t] = nd[t];
-      }
-      dump.pred[row] = pred;
-    }
-  }
-
-  // Workgroup merge of the moments in a fixed order (deterministic).
-  red[tid] = mo;
-  __syncthreads();
-#pragma unroll
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = mom_merge(red[tid], red[tid + s]);
-    __syncthreads();
-  }
-  if (tid == 0) partial[R.slot_base + tile] = red[0];
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// many targets per neighbour search (causal matrix)
-// ---------------------------------------------------------------------------
-//
-// One neighbour search over the manifold of series a serves the prediction of
-// every other series b (the library draw does not depend on the series).
-// Per target, the tile's observed/predicted pairs are reduced as sums of
-// values shifted by the target's first embedded value (n, s_o, s_p, s_oo,
-// s_pp, s_op) plus exact min/max of each side (so constant series give NaN
-// exactly), first over the wavefront by a fixed butterfly, then over the
-// four wavefronts in order.
-
-struct Sums {
-  double v[10];   // n, so, sp, soo, spp, sop, min o, max o, min p, max p
-};
-
-__device__ __forceinline__ void sums_merge(Sums& a, const Sums& b) {
-#pragma unroll
-  for (int i = 0; i < 6; ++i) a.v[i] += b.v[i];
-  a.v[6] = fmin(a.v[6], b.v[6]);
-  a.v[7] = fmax(a.v[7], b.v[7]);
-  a.v[8] = fmin(a.v[8], b.v[8]);
-  a.v[9] = fmax(a.v[9], b.v[9]);
-}
-
-__device__ __forceinline__ void sums_init(Sums& su) {
-#pragma unroll
-  for (int i = 0; i < 6; ++i) su.v[i] = 0.0;
-  su.v[6] = su.v[8] = __builtin_inf();
-  su.v[7] = su.v[9] = -__builtin_inf();
-}
-
-__device__ __forceinline__ void sums_add(Sums& su, double o, double pred, double shift) {
-  const double a = o - shift, p = pred - shift;
-  su.v[0] += 1.0;
-  su.v[1] += a;
-  su.v[2] += p;
-  su.v[3] += a * a;
-  su.v[4] += p * p;
-  su.v[5] += a * p;
-  su.v[6] = fmin(su.v[6], o);
-  su.v[7] = fmax(su.v[7], o);
-  su.v[8] = fmin(su.v[8], pred);
-  su.v[9] = fmax(su.v[9], pred);
-}
-
-// Order a wavefront's LDS accesses (its lanes read what other lanes wrote).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// LDS of the many-target item: per wavefront, one query set's neighbours
-// (w double [K][64], row offsets nj*mp int32 [K][64], qi*mp int32 [64]);
-// reused afterwards for the wavefronts' per-target sums (Sums [kWaves][64]).
-// A row offset fits in int32: it is below N*mp <= M*N + N, and the planner
-// caps M*N at INT32_MAX/2.
-template <int E>
-struct MultiLds {
-  static constexpr int K = E + 1;
-  static constexpr int kWave = 64 * (K * 12 + 4);
-  static constexpr int kStage = kWaves * kWave;
-  static constexpr int kRed = kWaves * 64 * (int)sizeof(Sums);
-  static constexpr int kBytes = kStage > kRed ? kStage : kRed;
-};
-
-template <int E, int Q, int MODE, bool TBL>
-__device__ __forceinline__ void crossmap_multi_item(
-    const Realization& R, int tile, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tt, int m_series, int self,
-    Sums* __restrict__ partial, int query_set, int window, unsigned char* lds,
-    const TableArgs& ta, uint32_t* tlds) {
-  constexpr int K = E + 1;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int mp = target_stride(m_series);
-  const int64_t off = (int64_t)(E - 1) * R.tau;
-
-  if constexpr (TBL)
-    if (R.table_off >= 0 && ta.words > 0) table_bitmask(R, pj_pool, tlds);
-  ScanState<E, Q, MODE> S;
-  scan_library<E, Q, MODE, TBL>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
-                                query_set, window, ta, tlds, S);
-
-  double w[Q][K];
-  int32_t nj[Q][K];
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    float nd[K];
-    select_neighbors<E, Q, MODE>(S, m, nd, nj[m]);
-    simplex_weights<K>(nd, w[m]);
-  }
-
-  // Per-target stage.  Row t of the time-major table holds every series'
-  // value at time t.  Lane b of a wavefront owns target b0 + b and walks the
-  // wavefront's queries (staged in LDS one query set at a time): each
-  // neighbour's row is then read by one coalesced load for all 64 targets.
-  // A target's sums are shifted by its first embedded value (time off).
-  unsigned char* stage = lds + wave * MultiLds<E>::kWave;
-  double* __restrict__ sw = reinterpret_cast<double*>(stage);
-  int32_t* __restrict__ srow = reinterpret_cast<int32_t*>(stage + 64 * K * 8);
-  int32_t* __restrict__ sqrow = reinterpret_cast<int32_t*>(stage + 64 * K * 12);
-  Sums* __restrict__ red = reinterpret_cast<Sums*>(lds);
-  const double* __restrict__ T = tt + off * mp;
-  for (int b0 = 0; b0 < m_series; b0 += 64) {
-    const int b = b0 + lane;
-    const bool act = b < m_series;
-    const double* __restrict__ Tb = T + (act ? b : 0);
-    const double shift = Tb[0];
-    Sums su;
-    sums_init(su);
-#pragma unroll
-    for (int m = 0; m < Q; ++m) {
-      // valid queries are a prefix of the lanes (the tail of the last tile
-      // is invalid)
-      const int nq = __popcll(__builtin_amdgcn_ballot_w64(S.qi[m] >= 0));
-      sqrow[lane] = S.qi[m] * mp;
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        srow[t * 64 + lane] = nj[m][t] * mp;
-        sw[t * 64 + lane] = w[m][t];
-      }
-      wave_sync();
-      if (act) {
-        // two queries per step, every load issued before any is used
-        int q = 0;
-        for (; q + 2 <= nq; q += 2) {
-          double v[2][K], o[2];
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-#pragma unroll
-            for (int t = 0; t < K; ++t) v[u][t] = Tb[srow[t * 64 + q + u]];
-            o[u] = Tb[sqrow[q + u]];
-          }
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            double pred = 0.0;
-#pragma unroll
-            for (int t = 0; t < K; ++t) pred += sw[t * 64 + q + u] * v[u][t];
-            sums_add(su, o[u], pred, shift);
-          }
-        }
-        if (q < nq) {
-          double v[K];
-#pragma unroll
-          for (int t = 0; t < K; ++t) v[t] = Tb[srow[t * 64 + q]];
-          const double o = Tb[sqrow[q]];
-          double pred = 0.0;
-#pragma unroll
-          for (int t = 0; t < K; ++t) pred += sw[t * 64 + q] * v[t];
-          sums_add(su, o, pred, shift);
-        }
-      }
-      wave_sync();
-    }
-    // wavefronts' sums -> LDS (over the staging area), merged in order
-    __syncthreads();
-    red[wave * 64 + lane] = su;
-    __syncthreads();
-    if (wave == 0 && act && b != self) {
-      Sums tot = red[lane];
-#pragma unroll
-      for (int wv = 1; wv < kWaves; ++wv) sums_merge(tot, red[wv * 64 + lane]);
-      partial[(R.slot_base + tile) * m_series + b] = tot;
-    }
-    __syncthreads();
-  }
-}
-
-// Build one row of a distance indexing table (one workgroup per row i): the
-// first w points j of [0, n_e) in ascending (d2(i, j), j) order.  d2 is the
-// cross-map kernel's binary32 distance; its bit pattern orders like its value
-// (d2 >= +0), so the w-th smallest value T is found by a three-pass radix
-// select on the bits (11, 11 and 10 bits, histograms in LDS), recomputing
-// the distances on each pass.  Then every j with d2 < T is kept, plus the
-// lowest-index ones with d2 == T up to w in all, and the w keys (d2 bits,
-// j) are sorted by a bitonic network in LDS.  Row stride: w rounded up to a
-// multiple of 4, padded with -1.
-constexpr int kTableMaxW = 1024;
-
-template <int E>
-__global__ __launch_bounds__(kBlock) void k_table_build(const TableJob* __restrict__ jobs,
-                                                        const float* __restrict__ emb_pool,
-                                                        int32_t* __restrict__ table_pool) {
-  __shared__ uint32_t hist[2048];
-  __shared__ uint64_t keys[kTableMaxW];
-  __shared__ uint32_t s_sel[2];
-  __shared__ int s_wave[kBlock / 64];
-  __shared__ int s_lt;
-  const TableJob J = jobs[blockIdx.y];
-  const int i = blockIdx.x;
-  if (i >= J.n_e) return;                       // uniform: whole workgroup
-  const int tid = threadIdx.x;
-  const float* __restrict__ emb = emb_pool + J.emb_off;
-  float q[E];
-#pragma unroll
-  for (int k = 0; k < E; ++k) q[k] = emb[(int64_t)i * E + k];
-  const int n = J.n_e;
-  const int w = J.w;
-
-  uint32_t prefix = 0, mask = 0;
-  uint32_t need = (uint32_t)w;                  // rank of T among the matching values
-  for (int pass = 0; pass < 3; ++pass) {
-    const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-    const int nbins = pass == 2 ? 1024 : 2048;
-    for (int b = tid; b < nbins; b += kBlock) hist[b] = 0u;
-    __syncthreads();
-    for (int j = tid; j < n; j += kBlock) {
-      const uint32_t u = __float_as_uint(sqdist<E>(q, emb + (int64_t)j * E));
-      if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & (nbins - 1)], 1u);
-    }
-    __syncthreads();
-    if (tid < 64) {
-      // bin holding the need-th value: lanes own nbins/64 consecutive bins
-      const int per = nbins / 64;
-      uint32_t loc = 0;
-      for (int b = 0; b < per; ++b) loc += hist[tid * per + b];
-      uint32_t inc = loc;
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o, 64);
-        if (tid >= o) inc += y;
-      }
-      const uint32_t exc = inc - loc;
-      if (exc < need && need <= inc) {
-        uint32_t c = exc;
-        for (int b = 0; b < per; ++b) {
-          const uint32_t h = hist[tid * per + b];
-          if (c + h >= need) {
-            s_sel[0] = (uint32_t)(tid * per + b);
-            s_sel[1] = c;
-            break;
-          }
-          c += h;
-        }
-      }
-    }
-    __syncthreads();
-    prefix |= s_sel[0] << shift;
-    mask |= (uint32_t)(nbins - 1) << shift;
-    need -= s_sel[1];
-    __syncthreads();
-  }
-  // prefix = T (all 32 bits fixed); `need` values equal to T are taken,
-  // the w - need values below T all are.
-  const uint32_t T = prefix;
-  if (tid == 0) s_lt = 0;
-  __syncthreads();
-  int eq_seen = 0;
-  for (int base = 0; base < n; base += kBlock) {
-    const int j = base + tid;
-    const uint32_t u = j < n ? __float_as_uint(sqdist<E>(q, emb + (int64_t)min(j, n - 1) * E))
-                             : 0xffffffffu;
-    const bool lt = j < n && u < T;
-    const bool eq = j < n && u == T;
-    if (lt) {
-      const int pos = atomicAdd(&s_lt, 1);
-      if (pos < w) keys[pos] = ((uint64_t)u << 32) | (uint32_t)j;
-    }
-    int tot;
-    const int r = block_rank(eq, s_wave, tot);
-    const int pe = w - (int)need + eq_seen + r;
-    if (eq && eq_seen + r < (int)need && pe >= 0 && pe < w)
-      keys[pe] = ((uint64_t)u << 32) | (uint32_t)j;
-    eq_seen += tot;
-  }
-  // bitonic sort of keys[0..P), P = the power of two >= w, padded with ~0
-  int P = 1;
-  while (P < w) P <<= 1;
-  for (int x = w + tid; x < P; x += kBlock) keys[x] = ~0ull;
-  __syncthreads();
-  for (int size = 2; size <= P; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int x = tid; x < P / 2; x += kBlock) {
-        const int lo = 2 * x - (x & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t a = keys[lo], b = keys[hi];
-        if ((a > b) == up) {
-          keys[lo] = b;
-          keys[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  const int rs = table_stride(w);
-  int32_t* __restrict__ row = table_pool + J.out_off + (int64_t)i * rs;
-  for (int x = tid; x < rs; x += kBlock) row[x] = x < w ? (int32_t)(keys[x] & 0xffffffffu) : -1;
-}
-
-// ---------------------------------------------------------------------------
-// nested libraries: one scan per chain, a snapshot per library size
-// ---------------------------------------------------------------------------
-//
-// A chain holds the libraries of one (E, tau, r, direction): the prefixes of
-// one ordering, split into segments at the library sizes (segment k holds
-// the points between sizes k-1 and k, gathered in visiting order with its
-// own scan starts).  The running lists after segments 0..k are exactly the
-// first E+1 candidates of the library of size k (a list only ever keeps the
-// smallest keys seen), so after each segment every query predicts from them
-// and the tile's moments for that size are merged and stored.
-template <int E, int Q, int MODE>
-__device__ __forceinline__ void nested_item(
-    const Realization& R, int tile, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tgt_pool, const int32_t* __restrict__ seg_pool,
-    Moments* __restrict__ partial, int window, Moments* red) {
-  constexpr int K = E + 1;
-  const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
-  const float* __restrict__ emb = emb_pool + R.emb_off;
-  const float* __restrict__ pts = pts_pool + R.pts_off;
-  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
-  const int32_t* __restrict__ qord = qord_pool + R.qord_off;
-  const double* __restrict__ tgt = tgt_pool + R.tgt_off;
-  const int32_t* __restrict__ seg = seg_pool + R.seg_off;
-  const int64_t off = (int64_t)(E - 1) * R.tau;
-
-  ScanState<E, Q, MODE> S;
-  const bool any = scan_queries<E, Q, MODE>(R, tile, wave, lane, emb, pj, qord, 0, S);
-  for (int k = 0; k < R.n_seg; ++k) {
-    const int b0 = seg[k], b1 = seg[k + 1];
-    const int64_t slot = R.slot_base + (int64_t)k * R.n_tiles + tile;
-    if (any)
-      scan_range<E, Q, MODE>(pts + (int64_t)b0 * E, pj + b0, b1 - b0,
-                             start_pool[slot * kWaves + wave], window, S);
-    Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int m = 0; m < Q; ++m) {
-      if (S.qi[m] < 0) continue;
-      float nd[K];
-      int32_t nj[K];
-      select_neighbors<E, Q, MODE>(S, m, nd, nj);
-      double w[K];
-      simplex_weights<K>(nd, w);
-      double pred = 0.0;
-#pragma unroll
-      for (int t = 0; t < K; ++t) pred += w[t] * tgt[nj[t] + off];
-      mom_add(mo, tgt[S.qi[m] + off], pred);
-    }
-    red[tid] = mo;
-    __syncthreads();
-#pragma unroll
-    for (int s2 = kBlock / 2; s2 > 0; s2 >>= 1) {
-      if (tid < s2) red[tid] = mom_merge(red[tid], red[tid + s2]);
-      __syncthreads();
-    }
-    if (tid == 0) partial[slot] = red[0];
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// E-sweep sharing: one scan serves every E <= EMAX
-// ---------------------------------------------------------------------------
-//
-// With the option, every E of a sweep uses the points of E_max's embedding
-// (their first E coordinates) and the same libraries.  The binary32 chain of
-// a pair after k coordinates is exactly that pair's d2 for E = k (the chain
-// runs in the same order from +0), so one pass over the library serves all
-// of them; each E keeps its own running list of E+1 keys (lists packed in
-// one array: E's list at offset (E-1)(E+2)/2).
-//
-// Fast path per group of G candidates: the chains, and per (query, E) the
-// smallest partial sum of the group; one compare per (query, E) against the
-// running E+1-th key decides whether E's list can change.  Only then are the
-// group's chains recomputed to E coordinates (the same sequence of binary32
-// operations, so the same values) and the candidates inserted, with the
-// exclusions checked exactly.
-
-template <int EMAX>
-struct SharedLists {
-  static constexpr int kTotal = EMAX * (EMAX + 3) / 2;
-  static constexpr int off(int e) { return (e - 1) * (e + 2) / 2; }
-};
-
-template <int EMAX, int Q>
-struct SharedState {
-  float qc[Q][EMAX];
-  int qi[Q];
-  double key[Q][SharedLists<EMAX>::kTotal];
-};
-
-template <int KS, int OFF, int TOT>
-__device__ __forceinline__ void insert_at(double (&key)[TOT], double c) {
-#pragma unroll
-  for (int m = KS - 1; m >= 1; --m) key[OFF + m] = kmin(kmax(key[OFF + m - 1], c), key[OFF + m]);
-  key[OFF] = kmin(key[OFF], c);
-}
-
-// d2 of candidate g to E coordinates.
-template <int EMAX, int G, int E>
-__device__ __forceinline__ float shared_d2(const Chunk<EMAX, G>& ch, int g,
-                                           const float (&q)[EMAX]) {
-  float d = q[0] - ch.p[g][0];
-  float acc = d * d;
-#pragma unroll
-  for (int k = 1; k < E; ++k) {
-    d = q[k] - ch.p[g][k];
-    acc = __builtin_fmaf(d, d, acc);
-  }
-  return acc;
-}
-
-// Slow path of list E: recompute the group's chains to E coordinates and
-// insert what enters E's list (exclusions checked exactly).
-template <int EMAX, int Q, int MODE, int G, int E>
-__device__ __forceinline__ void shared_lists(const Chunk<EMAX, G>& ch, const float (&mn)[Q][EMAX],
-                                             int window, SharedState<EMAX, Q>& S) {
-  constexpr int TOT = SharedLists<EMAX>::kTotal;
-  constexpr int OFF = SharedLists<EMAX>::off(E);
-  constexpr int KS = E + 1;
-  bool hit = false;
-#pragma unroll
-  for (int m = 0; m < Q; ++m) hit |= mn[m][E - 1] <= key_d2(S.key[m][OFF + KS - 1]);
-  if (__builtin_amdgcn_ballot_w64(hit)) {
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-      for (int m = 0; m < Q; ++m) {
-        const float d2 = shared_d2<EMAX, G, E>(ch, g, S.qc[m]);
-        bool ok = d2 <= key_d2(S.key[m][OFF + KS - 1]);
-        if (MODE == kExclSelf) ok = ok && ch.j[g] != S.qi[m];
-        if (MODE == kWindow) {
-          const int dj = ch.j[g] - S.qi[m];
-          ok = ok && (dj > window || dj < -window);
-        }
-        if (ok) insert_at<KS, OFF, TOT>(S.key[m], make_key(d2, ch.j[g]));
-      }
-  }
-  if constexpr (E < EMAX) shared_lists<EMAX, Q, MODE, G, E + 1>(ch, mn, window, S);
-}
-
-// Fast path: every chain of the group and, per (query, E), its smallest
-// partial sum, then one check per list.
-template <int EMAX, int Q, int MODE, int G>
-__device__ __forceinline__ void shared_chunk(const Chunk<EMAX, G>& ch, int window,
-                                             SharedState<EMAX, Q>& S) {
-  float mn[Q][EMAX];
-#pragma unroll
-  for (int g = 0; g < G; ++g)
-#pragma unroll
-    for (int m = 0; m < Q; ++m) {
-      float d = S.qc[m][0] - ch.p[g][0];
-      float acc = d * d;
-      if (MODE == kWindow) {
-        // an excluded pair never raises a trigger (checked exactly on insert)
-        const int dj = ch.j[g] - S.qi[m];
-        if (dj <= window && dj >= -window) acc = __builtin_inff();
-      }
-      mn[m][0] = g == 0 ? acc : fminf(mn[m][0], acc);
-#pragma unroll
-      for (int k = 1; k < EMAX; ++k) {
-        d = S.qc[m][k] - ch.p[g][k];
-        acc = __builtin_fmaf(d, d, acc);
-        mn[m][k] = g == 0 ? acc : fminf(mn[m][k], acc);
-      }
-    }
-  shared_lists<EMAX, Q, MODE, G, 1>(ch, mn, window, S);
-}
-
-template <int EMAX, int Q, int MODE, int G>
-__device__ __forceinline__ void shared_group(const float* __restrict__ pts,
-                                             const int32_t* __restrict__ pj, int c, int window,
-                                             SharedState<EMAX, Q>& S) {
-  Chunk<EMAX, G> ch;
-  load_chunk<EMAX, G>(ch, pts, pj, c);
-  shared_chunk<EMAX, Q, MODE, G>(ch, window, S);
-}
-
-// Prediction of list E for each of the lane's queries, the tile's moments
-// merged over the workgroup and stored in E's slots; then the next E.
-template <int EMAX, int Q, int E>
-__device__ __forceinline__ void shared_snapshot(const Realization& R, int tile,
-                                                const double* __restrict__ tgt, int64_t off,
-                                                const SharedState<EMAX, Q>& S,
-                                                Moments* __restrict__ partial, Moments* red) {
-  constexpr int K = E + 1;
-  constexpr int OFF = SharedLists<EMAX>::off(E);
-  const int tid = threadIdx.x;
-  Moments mo = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    if (S.qi[m] < 0) continue;
-    float nd[K];
-    double w[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) nd[t] = key_d2(S.key[m][OFF + t]);
-    simplex_weights<K>(nd, w);
-    double pred = 0.0;
-#pragma unroll
-    for (int t = 0; t < K; ++t) pred += w[t] * tgt[key_j(S.key[m][OFF + t]) + off];
-    mom_add(mo, tgt[S.qi[m] + off], pred);
-  }
-  red[tid] = mo;
-  __syncthreads();
-#pragma unroll
-  for (int s2 = kBlock / 2; s2 > 0; s2 >>= 1) {
-    if (tid < s2) red[tid] = mom_merge(red[tid], red[tid + s2]);
-    __syncthreads();
-  }
-  if (tid == 0) partial[R.slot_base + (int64_t)(E - 1) * R.n_tiles + tile] = red[0];
-  __syncthreads();
-  if constexpr (E < EMAX) shared_snapshot<EMAX, Q, E + 1>(R, tile, tgt, off, S, partial, red);
-}
-
-template <int EMAX, int MODE>
-__device__ __forceinline__ void shared_item(
-    const Realization& R, int tile, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tgt_pool, Moments* __restrict__ partial, int window,
-    Moments* red) {
-  constexpr int TOT = SharedLists<EMAX>::kTotal;
-  constexpr int Q = kSharedQ[EMAX];
-  constexpr int G = kSharedG[EMAX];
-  constexpr int QT = kBlock * Q;
-  constexpr int QW = 64 * Q;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const float* __restrict__ emb = emb_pool + R.emb_off;
-  const float* __restrict__ pts = pts_pool + R.pts_off;
-  const int32_t* __restrict__ pj = pj_pool + R.pj_off;
-  const int32_t* __restrict__ qord = qord_pool + R.qord_off;
-  const double* __restrict__ tgt = tgt_pool + R.tgt_off;
-  const int64_t off = (int64_t)(EMAX - 1) * R.tau;   // time of common point 0
-  const int L = R.l_eff;
-
-  SharedState<EMAX, Q> S;
-  bool any = false;
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    const int qq = tile * QT + wave * QW + m * 64 + lane;
-    const bool valid = qq < R.n_query;
-    any |= valid;
-    const int i = valid ? qord[qq] : 0;
-    S.qi[m] = valid ? i : -1;
-#pragma unroll
-    for (int k = 0; k < EMAX; ++k) S.qc[m][k] = emb[(int64_t)i * EMAX + k];
-#pragma unroll
-    for (int s = 0; s < TOT; ++s) S.key[m][s] = empty_key();
-  }
-
-  if (__builtin_amdgcn_ballot_w64(any)) {
-    int s0 = start_pool[(R.slot_base + tile) * kWaves + wave];
-    s0 = min(max(s0, 0), L);
-    int f = s0, b = s0;
-    const int both = min((L - s0) / G, s0 / G);
-    if (both > 0) {
-      Chunk<EMAX, G> A, B;
-      load_chunk<EMAX, G>(A, pts, pj, f);
-      for (int k = 0; k < both; ++k) {
-        settle_chunk<EMAX, G>(A);
-        __builtin_amdgcn_sched_barrier(0);
-        load_chunk<EMAX, G>(B, pts, pj, b - G);
-        __builtin_amdgcn_sched_barrier(0);
-        shared_chunk<EMAX, Q, MODE, G>(A, window, S);
-        f += G;
-        settle_chunk<EMAX, G>(B);
-        __builtin_amdgcn_sched_barrier(0);
-        load_chunk<EMAX, G>(A, pts, pj, k + 1 < both ? f : f - G);
-        __builtin_amdgcn_sched_barrier(0);
-        shared_chunk<EMAX, Q, MODE, G>(B, window, S);
-        b -= G;
-      }
-    }
-    for (; f + G <= L; f += G) shared_group<EMAX, Q, MODE, G>(pts, pj, f, window, S);
-    for (; b - G >= 0; b -= G) shared_group<EMAX, Q, MODE, G>(pts, pj, b - G, window, S);
-    for (; f < L; ++f) shared_group<EMAX, Q, MODE, 1>(pts, pj, f, window, S);
-    for (; b > 0; --b) shared_group<EMAX, Q, MODE, 1>(pts, pj, b - 1, window, S);
-  }
-  shared_snapshot<EMAX, Q, 1>(R, tile, tgt, off, S, partial, red);
-}
-
-// Work items are taken in list order (the host lists them longest first).
-// With next == nullptr each workgroup takes items blockIdx.x, +gridDim.x, ...;
-// otherwise workgroups pull the next item from an atomic counter that starts
-// at zero (a persistent grid).
-// Workgroups are dispatched to the chip's 8 XCDs round-robin (workgroup b
-// runs on XCD b mod 8), and each XCD has an L2 of its own.  The items of one
-// realization are consecutive and all read its library, so each XCD takes
-// runs of kXcdRun consecutive items: within every group of 8*kXcdRun
-// workgroups, workgroup b takes item  group + (b mod 8)*kXcdRun + (b/8) mod
-// kXcdRun.  Workgroups past the last whole group keep their own index; the
-// map is a permutation of [0, grid), so the item set is unchanged.
-constexpr int kXcds = 8;
-constexpr int kXcdRun = 16;
-__device__ __forceinline__ int xcd_item(int b, int grid) {
-  constexpr int span = kXcds * kXcdRun;
-  const int full = grid / span * span;
-  if (b >= full) return b;
-  const int base = b / span * span;
-  const int r = b - base;
-  return base + (r % kXcds) * kXcdRun + r / kXcds;
-}
-
-template <int E, int Q, int MODE, bool DUMP, bool TBL>
-__global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(kTuneW[E] > 0 ? kTuneW[E] : 1, 8))) void k_crossmap(
-    const Realization* __restrict__ rzs, const Item* __restrict__ items,
-    int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tgt_pool, Moments* __restrict__ partial,
-    int query_set, int window, Dump dump, TableArgs ta) {
-  __shared__ Moments red[kBlock];
-  __shared__ int s_next;
-  extern __shared__ uint32_t table_lds[];   // bitmask words, then accepted indices
-  int it = xcd_item(blockIdx.x, gridDim.x);
-  while (it < n_items) {
-    const Item I = items[it];
-    const Realization R = rzs[I.rz];
-    crossmap_item<E, Q, MODE, DUMP, TBL>(R, I.tile, emb_pool, pts_pool, pj_pool,
-                                    qord_pool, start_pool, tgt_pool, partial,
-                                    query_set, window, dump, red, ta, table_lds);
-    if (next == nullptr) {
-      it += gridDim.x;
-    } else {
-      if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(next, 1);
-      __syncthreads();
-      it = __builtin_amdgcn_readfirstlane(s_next);
-      __syncthreads();
-    }
-  }
-}
-
-// Causal-matrix form: realization rz searches the manifold of series
-// R.emb_off's owner (index self_of[rz]) and predicts all m_series series.
-template <int E, int Q, int MODE, bool TBL>
-__global__ __launch_bounds__(kBlock) void k_crossmap_multi(
-    const Realization* __restrict__ rzs, const int32_t* __restrict__ self_of,
-    const Item* __restrict__ items, int n_items, int* __restrict__ next,
-    const float* __restrict__ emb_pool, const float* __restrict__ pts_pool,
-    const int32_t* __restrict__ pj_pool, const int32_t* __restrict__ qord_pool,
-    const int32_t* __restrict__ start_pool, const double* __restrict__ tt,
-    int m_series, Sums* __restrict__ partial, int query_set, int window, TableArgs ta) {
-  __shared__ __align__(16) unsigned char lds[MultiLds<E>::kBytes];
-  __shared__ int s_next;
-  extern __shared__ uint32_t table_lds[];   // bitmask words, then accepted indices
-  int it = xcd_item(blockIdx.x, gridDim.x);
-  while (it < n_items) {
-    const Item I = items[it];
-    const Realization R = rzs[I.rz];
-    crossmap_multi_item<E, Q, MODE, TBL>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool,
-                                    start_pool, tt, m_series, self_of[I.rz], partial,
-                                    query_set, window, lds, ta, table_lds);
-    if (next == nullptr) {
-      it += gridDim.x;
-    } else {
-      if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(next, 1);
-      __syncthreads();
-      it = __builtin_amdgcn_readfirstlane(s_next);
-      __syncthreads();
-    }
-  }
-}
-
-// rho[self][b] of every realization from the per-tile sums; NaN on the
-// diagonal and when either side is constant.
-template <int E, int Q, int MODE>
-__global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(kNestedW[E] > 0 ? kNestedW[E] : 1, 8))) void k_crossmap_nested(
-    const Realization* __restrict__ rzs, const Item* __restrict__ items,
-    int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tgt_pool, const int32_t* __restrict__ seg_pool,
-    Moments* __restrict__ partial, int window) {
-  __shared__ Moments red[kBlock];
-  __shared__ int s_next;
-  int it = xcd_item(blockIdx.x, gridDim.x);
-  while (it < n_items) {
-    const Item I = items[it];
-    const Realization R = rzs[I.rz];
-    nested_item<E, Q, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
-                            tgt_pool, seg_pool, partial, window, red);
-    if (next == nullptr) {
-      it += gridDim.x;
-    } else {
-      if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(next, 1);
-      __syncthreads();
-      it = __builtin_amdgcn_readfirstlane(s_next);
-      __syncthreads();
-    }
-  }
-}
-
-template <int EMAX, int MODE>
-__global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(kSharedW[EMAX] > 0 ? kSharedW[EMAX] : 1, 8)))
-void k_crossmap_shared(
-    const Realization* __restrict__ rzs, const Item* __restrict__ items,
-    int n_items, int* __restrict__ next, const float* __restrict__ emb_pool,
-    const float* __restrict__ pts_pool, const int32_t* __restrict__ pj_pool,
-    const int32_t* __restrict__ qord_pool, const int32_t* __restrict__ start_pool,
-    const double* __restrict__ tgt_pool, Moments* __restrict__ partial, int window) {
-  __shared__ Moments red[kBlock];
-  __shared__ int s_next;
-  int it = xcd_item(blockIdx.x, gridDim.x);
-  while (it < n_items) {
-    const Item I = items[it];
-    const Realization R = rzs[I.rz];
-    shared_item<EMAX, MODE>(R, I.tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
-                            tgt_pool, partial, window, red);
-    if (next == nullptr) {
-      it += gridDim.x;
-    } else {
-      if (threadIdx.x == 0) s_next = (int)gridDim.x + atomicAdd(next, 1);
-      __syncthreads();
-      it = __builtin_amdgcn_readfirstlane(s_next);
-      __syncthreads();
-    }
-  }
-}
-
 __global__ void k_finalize_multi(const Realization* __restrict__ rzs,
                                  const int32_t* __restrict__ self_of, int64_t n_rz,
                                  int m_series, const Sums* __restrict__ partial,
@@ -1637,69 +406,10 @@ __global__ void k_finalize(const Realization* __restrict__ rzs, int64_t n_rz,
   out[R.out_index] = rho;
 }
 
-// ---------------------------------------------------------------------------
-// kernel table
-// ---------------------------------------------------------------------------
-
-using CrossmapFn = void (*)(const Realization*, const Item*, int, int*,
-                            const float*, const float*, const int32_t*,
-                            const int32_t*, const int32_t*, const double*,
-                            Moments*, int, int, Dump, TableArgs);
-
-template <int E, int Q, bool DUMP, bool TBL>
-struct QSetT {
-  static CrossmapFn get(int mode) {
-    switch (mode) {
-      case kExclSelf: return k_crossmap<E, Q, kExclSelf, DUMP, TBL>;
-      case kKeepSelf: return k_crossmap<E, Q, kKeepSelf, DUMP, TBL>;
-      default: return k_crossmap<E, Q, kWindow, DUMP, TBL>;
-    }
-  }
-};
-
-template <int E, int Q>
-struct QSet {
-  static CrossmapFn get(int mode, bool dump, bool tbl) {
-    if (dump) return tbl ? QSetT<E, Q, true, true>::get(mode) : QSetT<E, Q, true, false>::get(mode);
-    return tbl ? QSetT<E, Q, false, true>::get(mode) : QSetT<E, Q, false, false>::get(mode);
-  }
-};
-
-// Queries per lane for the hot kernel (tuned per E: fewer when the running
-// lists are long so that registers stay within budget).
-template <int E>
-struct DefaultQ {
-  static constexpr int Q = kTuneQ[E];
-};
-
-static CrossmapFn crossmap_kernel(int E, int mode, bool dump, bool tbl, int* q_out) {
-  int q = 1;
-  CrossmapFn f = nullptr;
-  switch (E) {
-#define CCM_CASE(e)                                           \
-  case e:                                                     \
-    q = DefaultQ<e>::Q;                                       \
-    f = QSet<e, DefaultQ<e>::Q>::get(mode, dump, tbl);        \
-    break;
-    CCM_CASE(1) CCM_CASE(2) CCM_CASE(3) CCM_CASE(4) CCM_CASE(5)
-    CCM_CASE(6) CCM_CASE(7) CCM_CASE(8) CCM_CASE(9) CCM_CASE(10)
-#undef CCM_CASE
-    default: break;
-  }
-  if (q_out) *q_out = q;
-  return f;
-}
 
 // ---------------------------------------------------------------------------
 // host-side launchers (the runtime calls only these)
 // ---------------------------------------------------------------------------
-
-// Dynamic LDS of a cross-map launch whose realizations walk tables over at
-// most n_e points: the library bitmask, then E+1 accepted indices per lane.
-static inline int table_lds_words(int n_e) { return n_e > 0 ? (n_e + 31) / 32 : 0; }
-static inline size_t table_lds_bytes(int E, int n_e) {
-  return n_e > 0 ? (size_t)table_lds_words(n_e) * 4 + (size_t)(E + 1) * kBlock * 4 : 0;
-}
 
 static inline unsigned blocks_for(int64_t n, int per) {
   int64_t b = (n + per - 1) / per;
@@ -1712,11 +422,7 @@ int shared_queries_per_lane(int emax) {
   return emax >= 1 && emax <= kMaxE ? kSharedQ[emax] : 0;
 }
 
-int crossmap_queries_per_lane(int E) {
-  int q = 0;
-  crossmap_kernel(E, kExclSelf, false, false, &q);
-  return q;
-}
+int crossmap_queries_per_lane(int E) { return E >= 1 && E <= kMaxE ? kTuneQ[E] : 0; }
 
 hipError_t launch_ingest(const IngestJob* jobs, int n_jobs, int64_t max_n,
                          const double* src, float* dst, hipStream_t st) {
@@ -1789,50 +495,22 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
 hipError_t launch_table_build(int E, const TableJob* jobs, int n_jobs, int max_n_e,
                               const float* emb, int32_t* table, hipStream_t st) {
   if (n_jobs <= 0 || max_n_e <= 0) return hipSuccess;
-  const dim3 grid((unsigned)max_n_e, (unsigned)n_jobs);
   switch (E) {
-#define CCM_TCASE(e)                                                        \
-  case e:                                                                   \
-    k_table_build<e><<<grid, kBlock, 0, st>>>(jobs, emb, table);            \
-    break;
+#define CCM_TCASE(e) \
+  case e:            \
+    return launch_table_build_e<e>(jobs, n_jobs, max_n_e, emb, table, st);
     CCM_TCASE(1) CCM_TCASE(2) CCM_TCASE(3) CCM_TCASE(4) CCM_TCASE(5)
     CCM_TCASE(6) CCM_TCASE(7) CCM_TCASE(8) CCM_TCASE(9) CCM_TCASE(10)
 #undef CCM_TCASE
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_sample_nested(const NestedJob* jobs, int64_t n_jobs, int32_t* scratch,
                                 int32_t* out_pool, hipStream_t st) {
   if (n_jobs <= 0) return hipSuccess;
   k_sample_nested<<<(unsigned)n_jobs, kBlock, 0, st>>>(jobs, scratch, out_pool);
-  return hipGetLastError();
-}
-
-template <int E>
-static hipError_t launch_nested_e(int mode, int grid, const Realization* rzs,
-                                  const Item* items, int n_items, int* next,
-                                  const float* emb, const float* pts, const int32_t* pj,
-                                  const int32_t* qord, const int32_t* start, const double* tgt,
-                                  const int32_t* seg, Moments* partial, int window,
-                                  hipStream_t st) {
-  constexpr int Q = DefaultQ<E>::Q;
-  switch (mode) {
-    case kExclSelf:
-      k_crossmap_nested<E, Q, kExclSelf><<<grid, kBlock, 0, st>>>(
-          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, seg, partial, window);
-      break;
-    case kKeepSelf:
-      k_crossmap_nested<E, Q, kKeepSelf><<<grid, kBlock, 0, st>>>(
-          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, seg, partial, window);
-      break;
-    default:
-      k_crossmap_nested<E, Q, kWindow><<<grid, kBlock, 0, st>>>(
-          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, seg, partial, window);
-      break;
-  }
   return hipGetLastError();
 }
 
@@ -1854,29 +532,6 @@ hipError_t launch_crossmap_nested(int E, int mode, int grid, const Realization* 
     default:
       return hipErrorInvalidValue;
   }
-}
-
-template <int EMAX>
-static hipError_t launch_shared_e(int mode, int grid, const Realization* rzs,
-                                  const Item* items, int n_items, int* next,
-                                  const float* emb, const float* pts, const int32_t* pj,
-                                  const int32_t* qord, const int32_t* start, const double* tgt,
-                                  Moments* partial, int window, hipStream_t st) {
-  switch (mode) {
-    case kExclSelf:
-      k_crossmap_shared<EMAX, kExclSelf><<<grid, kBlock, 0, st>>>(
-          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial, window);
-      break;
-    case kKeepSelf:
-      k_crossmap_shared<EMAX, kKeepSelf><<<grid, kBlock, 0, st>>>(
-          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial, window);
-      break;
-    default:
-      k_crossmap_shared<EMAX, kWindow><<<grid, kBlock, 0, st>>>(
-          rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial, window);
-      break;
-  }
-  return hipGetLastError();
 }
 
 hipError_t launch_crossmap_shared(int emax, int mode, int grid, const Realization* rzs,
@@ -1907,46 +562,18 @@ hipError_t launch_crossmap(int E, int mode, int grid,
                            int window, Dump d, const int32_t* table, int table_n_e,
                            hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  CrossmapFn f = crossmap_kernel(E, mode, d.nbr != nullptr, table_n_e > 0, nullptr);
-  if (!f) return hipErrorInvalidValue;
-  const TableArgs ta{table, table_lds_words(table_n_e), 0};
-  hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), table_lds_bytes(E, table_n_e), st,
-                     rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial,
-                     query_set, window, d, ta);
-  return hipGetLastError();
-}
-
-template <int E>
-static hipError_t launch_multi_e(int mode, int grid, const Realization* rzs,
-                                 const int32_t* self_of, const Item* items, int n_items,
-                                 int* next, const float* emb, const float* pts,
-                                 const int32_t* pj, const int32_t* qord, const int32_t* start,
-                                 const double* tt, int m_series,
-                                 Sums* partial, int query_set, int window,
-                                 const int32_t* table, int table_n_e, hipStream_t st) {
-  constexpr int Q = DefaultQ<E>::Q;
-  const TableArgs ta{table, table_lds_words(table_n_e), 0};
-  const size_t dyn = table_lds_bytes(E, table_n_e);
-  using MultiFn = void (*)(const Realization*, const int32_t*, const Item*, int, int*,
-                           const float*, const float*, const int32_t*, const int32_t*,
-                           const int32_t*, const double*, int, Sums*, int, int, TableArgs);
-  MultiFn f;
-  const bool tbl = table_n_e > 0;
-  switch (mode) {
-    case kExclSelf:
-      f = tbl ? k_crossmap_multi<E, Q, kExclSelf, true> : k_crossmap_multi<E, Q, kExclSelf, false>;
-      break;
-    case kKeepSelf:
-      f = tbl ? k_crossmap_multi<E, Q, kKeepSelf, true> : k_crossmap_multi<E, Q, kKeepSelf, false>;
-      break;
+  switch (E) {
+#define CCM_CASE(e)                                                                         \
+  case e:                                                                                   \
+    return launch_crossmap_e<e>(mode, grid, rzs, items, n_items, next, emb, pts, pj, qord,  \
+                                start, tgt, partial, query_set, window, d, table, table_n_e, \
+                                st);
+    CCM_CASE(1) CCM_CASE(2) CCM_CASE(3) CCM_CASE(4) CCM_CASE(5)
+    CCM_CASE(6) CCM_CASE(7) CCM_CASE(8) CCM_CASE(9) CCM_CASE(10)
+#undef CCM_CASE
     default:
-      f = tbl ? k_crossmap_multi<E, Q, kWindow, true> : k_crossmap_multi<E, Q, kWindow, false>;
-      break;
+      return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), dyn, st, rzs, self_of, items,
-                     n_items, next, emb, pts, pj, qord, start, tt, m_series, partial,
-                     query_set, window, ta);
-  return hipGetLastError();
 }
 
 __global__ void k_transpose_targets(const double* __restrict__ s64, int m, int mp, int64_t n,
@@ -1974,12 +601,11 @@ hipError_t launch_crossmap_multi(int E, int mode, int grid, const Realization* r
                                  void* partial, int query_set, int window,
                                  const int32_t* table, int table_n_e, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  Sums* ps = static_cast<Sums*>(partial);
   switch (E) {
-#define CCM_MCASE(e)                                                                     \
-  case e:                                                                                \
+#define CCM_MCASE(e)                                                                      \
+  case e:                                                                                 \
     return launch_multi_e<e>(mode, grid, rzs, self_of, items, n_items, next, emb, pts, pj, \
-                             qord, start, tt, m_series, ps, query_set, window, table,   \
+                             qord, start, tt, m_series, partial, query_set, window, table,  \
                              table_n_e, st);
     CCM_MCASE(1) CCM_MCASE(2) CCM_MCASE(3) CCM_MCASE(4) CCM_MCASE(5)
     CCM_MCASE(6) CCM_MCASE(7) CCM_MCASE(8) CCM_MCASE(9) CCM_MCASE(10)

@@ -220,6 +220,59 @@ __device__ __forceinline__ void compute_chunk(
   }
 }
 
+// E = 1: d2 = fl(d * d) with d = fl(q - p) is a non-decreasing function of
+// |d|, so the smallest d2 of a group is fl(m * m) with m the smallest |d|:
+// the group check needs one subtraction and half a three-way minimum per
+// pair instead of a subtraction and a product.  A group that passes
+// recomputes its differences (the same values) and its exact d2.
+template <int Q, int MODE, int G>
+__device__ __forceinline__ void compute_chunk_e1(
+    const Chunk<1, G>& ch, const float (&qc)[Q][1], const int (&qi)[Q], int window,
+    double (&key)[Q][Slots<1, MODE>::KS]) {
+  constexpr int KS = Slots<1, MODE>::KS;
+  float a[Q];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) a[m] = __builtin_inff();
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      float v = qc[m][0] - ch.p[g][0];
+      if (MODE == kWindow) {
+        const int dj = ch.j[g] - qi[m];
+        if (dj <= window && dj >= -window) v = __builtin_nanf("");
+      }
+      a[m] = fminf(a[m], fabsf(v));
+    }
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    if (__builtin_amdgcn_ballot_w64(a[m] * a[m] <= key_d2(key[m][KS - 1]))) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const float v = qc[m][0] - ch.p[g][0];
+        const float d2 = v * v;
+        bool ok = d2 <= key_d2(key[m][KS - 1]);
+        if (MODE == kExclSelf) ok = ok && ch.j[g] != qi[m];
+        if (MODE == kWindow) {
+          const int dj = ch.j[g] - qi[m];
+          ok = ok && (dj > window || dj < -window);
+        }
+        if (ok) insert_key<KS>(key[m], make_key(d2, ch.j[g]));
+      }
+    }
+  }
+}
+
+template <int E, int Q, int MODE, int G>
+__device__ __forceinline__ void check_chunk(
+    const Chunk<E, G>& ch, const float (&qc)[Q][E], const int (&qi)[Q], int window,
+    double (&key)[Q][Slots<E, MODE>::KS]) {
+  if constexpr (E == 1)
+    compute_chunk_e1<Q, MODE, G>(ch, qc, qi, window, key);
+  else
+    compute_chunk<E, Q, MODE, G>(ch, qc, qi, window, key);
+}
+
 template <int E, int Q, int MODE, int G>
 __device__ __forceinline__ void scan_group(
     const float* __restrict__ pts, const int32_t* __restrict__ pj, int c,
@@ -227,7 +280,7 @@ __device__ __forceinline__ void scan_group(
     double (&key)[Q][Slots<E, MODE>::KS]) {
   Chunk<E, G> ch;
   load_chunk<E, G>(ch, pts, pj, c);
-  compute_chunk<E, Q, MODE, G>(ch, qc, qi, window, key);
+  check_chunk<E, Q, MODE, G>(ch, qc, qi, window, key);
 }
 
 // Queries of one item and their running candidate lists after the scan of
@@ -377,13 +430,13 @@ __device__ __forceinline__ void scan_range(const float* __restrict__ pts,
       __builtin_amdgcn_sched_barrier(0);
       load_chunk<E, G>(B, pts, pj, b - G);
       __builtin_amdgcn_sched_barrier(0);
-      compute_chunk<E, Q, MODE, G>(A, S.qc, S.qi, window, S.key);
+      check_chunk<E, Q, MODE, G>(A, S.qc, S.qi, window, S.key);
       f += G;
       settle_chunk<E, G>(B);
       __builtin_amdgcn_sched_barrier(0);
       load_chunk<E, G>(A, pts, pj, k + 1 < both ? f : f - G);
       __builtin_amdgcn_sched_barrier(0);
-      compute_chunk<E, Q, MODE, G>(B, S.qc, S.qi, window, S.key);
+      check_chunk<E, Q, MODE, G>(B, S.qc, S.qi, window, S.key);
       b -= G;
     }
   }
@@ -596,6 +649,77 @@ struct MultiLds {
   static constexpr int kBytes = kStage > kRed ? kStage : kRed;
 };
 
+// One block of 64 targets of the many-target stage (see below): lane b of
+// each wavefront accumulates target b0 + b over the wavefront's queries, set
+// by set, then the four wavefronts' sums are merged in order.
+template <int E, int Q, int MODE>
+__device__ __forceinline__ void multi_target_block(const ScanState<E, Q, MODE>& S,
+                                                   const Realization& R, int tile,
+                                                   const double* __restrict__ T, int b0,
+                                                   int m_series, int self, int mp,
+                                                   Sums* __restrict__ partial,
+                                                   unsigned char* lds) {
+  constexpr int K = E + 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char* stage = lds + wave * MultiLds<E>::kWave;
+  double* __restrict__ sw = reinterpret_cast<double*>(stage);
+  int32_t* __restrict__ srow = reinterpret_cast<int32_t*>(stage + 64 * K * 8);
+  int32_t* __restrict__ sqrow = reinterpret_cast<int32_t*>(stage + 64 * K * 12);
+  Sums* __restrict__ red = reinterpret_cast<Sums*>(lds);
+  const int b = b0 + lane;
+  const bool act = b < m_series;
+  const double* __restrict__ Tb = T + (act ? b : 0);
+  const double shift = Tb[0];
+  Sums su;
+  sums_init(su);
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    // valid queries are a prefix of the lanes (the tail of the last tile is
+    // invalid)
+    const int nq = __popcll(__builtin_amdgcn_ballot_w64(S.qi[m] >= 0));
+    {
+      float nd[K];
+      int32_t nj[K];
+      double w[K];
+      select_neighbors<E, Q, MODE>(S, m, nd, nj);
+      simplex_weights<K>(nd, w);
+      sqrow[lane] = S.qi[m] * mp;
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        srow[t * 64 + lane] = nj[t] * mp;
+        sw[t * 64 + lane] = w[t];
+      }
+    }
+    wave_sync();
+    if (act) {
+      // one query per step, its K + 1 loads issued before any is used
+      for (int q = 0; q < nq; ++q) {
+        double v[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) v[t] = Tb[srow[t * 64 + q]];
+        const double o = Tb[sqrow[q]];
+        double pred = 0.0;
+#pragma unroll
+        for (int t = 0; t < K; ++t) pred += sw[t * 64 + q] * v[t];
+        sums_add(su, o, pred, shift);
+      }
+    }
+    wave_sync();
+  }
+  // wavefronts' sums -> LDS (over the staging area), merged in order
+  __syncthreads();
+  red[wave * 64 + lane] = su;
+  __syncthreads();
+  if (wave == 0 && act && b != self) {
+    Sums tot = red[lane];
+#pragma unroll
+    for (int wv = 1; wv < kWaves; ++wv) sums_merge(tot, red[wv * 64 + lane]);
+    partial[(R.slot_base + tile) * m_series + b] = tot;
+  }
+  __syncthreads();
+}
+
 template <int E, int Q, int MODE, bool TBL>
 __device__ __forceinline__ void crossmap_multi_item(
     const Realization& R, int tile, const float* __restrict__ emb_pool,
@@ -617,88 +741,19 @@ __device__ __forceinline__ void crossmap_multi_item(
   scan_library<E, Q, MODE, TBL>(R, tile, emb_pool, pts_pool, pj_pool, qord_pool, start_pool,
                                 query_set, window, ta, tlds, S);
 
-  double w[Q][K];
-  int32_t nj[Q][K];
-#pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    float nd[K];
-    select_neighbors<E, Q, MODE>(S, m, nd, nj[m]);
-    simplex_weights<K>(nd, w[m]);
-  }
-
   // Per-target stage.  Row t of the time-major table holds every series'
   // value at time t.  Lane b of a wavefront owns target b0 + b and walks the
   // wavefront's queries (staged in LDS one query set at a time): each
   // neighbour's row is then read by one coalesced load for all 64 targets.
   // A target's sums are shifted by its first embedded value (time off).
-  unsigned char* stage = lds + wave * MultiLds<E>::kWave;
-  double* __restrict__ sw = reinterpret_cast<double*>(stage);
-  int32_t* __restrict__ srow = reinterpret_cast<int32_t*>(stage + 64 * K * 8);
-  int32_t* __restrict__ sqrow = reinterpret_cast<int32_t*>(stage + 64 * K * 12);
-  Sums* __restrict__ red = reinterpret_cast<Sums*>(lds);
+  // With at most 64 targets there is one block, and each query set's running
+  // list is dead once its weights are staged (fewer live registers).
   const double* __restrict__ T = tt + off * mp;
-  for (int b0 = 0; b0 < m_series; b0 += 64) {
-    const int b = b0 + lane;
-    const bool act = b < m_series;
-    const double* __restrict__ Tb = T + (act ? b : 0);
-    const double shift = Tb[0];
-    Sums su;
-    sums_init(su);
-#pragma unroll
-    for (int m = 0; m < Q; ++m) {
-      // valid queries are a prefix of the lanes (the tail of the last tile
-      // is invalid)
-      const int nq = __popcll(__builtin_amdgcn_ballot_w64(S.qi[m] >= 0));
-      sqrow[lane] = S.qi[m] * mp;
-#pragma unroll
-      for (int t = 0; t < K; ++t) {
-        srow[t * 64 + lane] = nj[m][t] * mp;
-        sw[t * 64 + lane] = w[m][t];
-      }
-      wave_sync();
-      if (act) {
-        // two queries per step, every load issued before any is used
-        int q = 0;
-        for (; q + 2 <= nq; q += 2) {
-          double v[2][K], o[2];
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-#pragma unroll
-            for (int t = 0; t < K; ++t) v[u][t] = Tb[srow[t * 64 + q + u]];
-            o[u] = Tb[sqrow[q + u]];
-          }
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            double pred = 0.0;
-#pragma unroll
-            for (int t = 0; t < K; ++t) pred += sw[t * 64 + q + u] * v[u][t];
-            sums_add(su, o[u], pred, shift);
-          }
-        }
-        if (q < nq) {
-          double v[K];
-#pragma unroll
-          for (int t = 0; t < K; ++t) v[t] = Tb[srow[t * 64 + q]];
-          const double o = Tb[sqrow[q]];
-          double pred = 0.0;
-#pragma unroll
-          for (int t = 0; t < K; ++t) pred += sw[t * 64 + q] * v[t];
-          sums_add(su, o, pred, shift);
-        }
-      }
-      wave_sync();
-    }
-    // wavefronts' sums -> LDS (over the staging area), merged in order
-    __syncthreads();
-    red[wave * 64 + lane] = su;
-    __syncthreads();
-    if (wave == 0 && act && b != self) {
-      Sums tot = red[lane];
-#pragma unroll
-      for (int wv = 1; wv < kWaves; ++wv) sums_merge(tot, red[wv * 64 + lane]);
-      partial[(R.slot_base + tile) * m_series + b] = tot;
-    }
-    __syncthreads();
+  if (m_series <= 64) {
+    multi_target_block<E, Q, MODE>(S, R, tile, T, 0, m_series, self, mp, partial, lds);
+  } else {
+    for (int b0 = 0; b0 < m_series; b0 += 64)
+      multi_target_block<E, Q, MODE>(S, R, tile, T, b0, m_series, self, mp, partial, lds);
   }
 }
 
@@ -1164,7 +1219,8 @@ __attribute__((amdgpu_waves_per_eu(kTuneW[E] > 0 ? kTuneW[E] : 1, 8))) void k_cr
 // Causal-matrix form: realization rz searches the manifold of series
 // R.emb_off's owner (index self_of[rz]) and predicts all m_series series.
 template <int E, int Q, int MODE, bool TBL>
-__global__ __launch_bounds__(kBlock) void k_crossmap_multi(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(kMultiW[E] > 0 ? kMultiW[E] : 1, 8))) void k_crossmap_multi(
     const Realization* __restrict__ rzs, const int32_t* __restrict__ self_of,
     const Item* __restrict__ items, int n_items, int* __restrict__ next,
     const float* __restrict__ emb_pool, const float* __restrict__ pts_pool,

@@ -45,7 +45,14 @@
 #define CCM_NESTED_W {0, 7, 6, 4, 4, 4, 5, 4, 4, 4, 4}
 #endif
 
+// Causal matrix: minimum wavefronts per SIMD of the many-target kernel (its
+// per-target stage holds more state than the plain scan's moments; 0: free).
+#ifndef CCM_MULTI_W
+#define CCM_MULTI_W {0, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5}
+#endif
+
 namespace ccmk {
+constexpr int kMultiW[11] = CCM_MULTI_W;
 constexpr int kNestedW[11] = CCM_NESTED_W;
 constexpr int kTuneQ[11] = CCM_TUNE_Q;
 constexpr int kTuneG[11] = CCM_TUNE_G;

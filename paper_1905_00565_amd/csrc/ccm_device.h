@@ -505,21 +505,21 @@ __device__ __forceinline__ void select_neighbors(const ScanState<E, Q, MODE>& S,
 // u = exp(-d / d_1) (or the zero-distance rule when d_1 = 0), w = u / sum u.
 template <int K>
 __device__ __forceinline__ void simplex_weights(const float (&nd)[K], double (&w)[K]) {
-  double dist[K], u[K];
+  // the distances are formed inside the loop (sqrt(x) == 0 exactly when
+  // x == 0), so no array of them stays live beside the weights
+  const double d0 = sqrt((double)nd[0]);
+  if (d0 > 0.0) {
 #pragma unroll
-  for (int t = 0; t < K; ++t) dist[t] = sqrt((double)nd[t]);
-  if (dist[0] > 0.0) {
-#pragma unroll
-    for (int t = 0; t < K; ++t) u[t] = exp(-dist[t] / dist[0]);
+    for (int t = 0; t < K; ++t) w[t] = exp(-sqrt((double)nd[t]) / d0);
   } else {
 #pragma unroll
-    for (int t = 0; t < K; ++t) u[t] = dist[t] == 0.0 ? 1.0 : 0.0;
+    for (int t = 0; t < K; ++t) w[t] = nd[t] == 0.0f ? 1.0 : 0.0;
   }
   double su = 0.0;
 #pragma unroll
-  for (int t = 0; t < K; ++t) su += u[t];
+  for (int t = 0; t < K; ++t) su += w[t];
 #pragma unroll
-  for (int t = 0; t < K; ++t) w[t] = u[t] / su;
+  for (int t = 0; t < K; ++t) w[t] = w[t] / su;
 }
 
 // DUMP (the test hook): every query's neighbours, squared distances and
@@ -693,7 +693,8 @@ __device__ __forceinline__ void multi_target_block(const ScanState<E, Q, MODE>& 
     }
     wave_sync();
     if (act) {
-      // one query per step, its K + 1 loads issued before any is used
+      // one query per step, its K + 1 loads issued before any is used (two
+      // per step measured no faster)
       for (int q = 0; q < nq; ++q) {
         double v[K];
 #pragma unroll

@@ -48,7 +48,7 @@
 // Causal matrix: minimum wavefronts per SIMD of the many-target kernel (its
 // per-target stage holds more state than the plain scan's moments; 0: free).
 #ifndef CCM_MULTI_W
-#define CCM_MULTI_W {0, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5}
+#define CCM_MULTI_W {0, 5, 5, 5, 5, 5, 5, 5, 5, 5, 4}
 #endif
 
 namespace ccmk {

@@ -107,6 +107,8 @@ def parse():
                     help="Poisson arrival rates as fractions of measured capacity")
     ap.add_argument("--serve-protocol", type=int, default=0,
                     help="1: run only the served form's full protocol and print it")
+    ap.add_argument("--protocol-loads", type=str, default="0.1,0.3,0.5,0.7,0.8,0.9,0.95",
+                    help="load points of --serve-protocol (a subset runs in less time)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device to device "
                          "once (a plain copy of known size for calibrating the "
@@ -398,17 +400,20 @@ def elasticity_leg(ctx, torch, dev, stream, reps=3):
     return out
 
 
-def _serve(srv, jobs, arrivals, flags=0):
+def _serve(srv, jobs, arrivals, flags=0, note=None):
     """Submit jobs at the given arrival times (seconds from now), wait for all;
-    returns (makespan, latencies submit->done, stats of each job)."""
+    returns (makespan, latencies submit->done, stats of each job).  With a
+    note, a progress line goes to stderr every 100 submissions."""
     t0 = time.perf_counter()
     tickets = []
-    for (X, Y, j), ta in zip(jobs, arrivals):
+    for k, ((X, Y, j), ta) in enumerate(zip(jobs, arrivals)):
         delay = ta - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
         tickets.append((srv.submit(X, Y, j["E"], j["tau"], j["L"], j["r"], j["seed"],
                                    flags=flags), j))
+        if note and (k + 1) % 100 == 0:
+            print(f"bench: {note}: {k + 1}/{len(jobs)} submitted", file=sys.stderr, flush=True)
     lat, stats = [], []
     for t, j in tickets:
         assert srv.wait(t) == capi.CCM_OK
@@ -437,7 +442,7 @@ def load_points(ctx, jobs, capacity, loads, seed, discard):
             rate = load * capacity
             gaps = np.random.default_rng([seed, 17, k]).exponential(1.0 / rate, len(jobs))
             arrivals = np.cumsum(gaps) - gaps[0]
-            make, lat, _ = _serve(srv, jobs, list(arrivals))
+            make, lat, _ = _serve(srv, jobs, list(arrivals), note=f"load {load}")
             kept = lat[discard:]
             pts.append({"load": load, "arrival_rate_jobs_per_sec": rate, "jobs": len(jobs),
                         "discarded": discard, "throughput_jobs_per_sec": len(jobs) / make,
@@ -567,7 +572,8 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = capi.Context(0)
     if a.serve_protocol:
-        print(json.dumps({"served_protocol": serve_protocol(ctx)}), flush=True)
+        loads = [float(v) for v in a.protocol_loads.split(",") if v]
+        print(json.dumps({"served_protocol": serve_protocol(ctx, loads=loads)}), flush=True)
         ctx.close()
         return
 

@@ -1177,7 +1177,10 @@ __device__ __forceinline__ void shared_item(
 // kXcdRun.  Workgroups past the last whole group keep their own index; the
 // map is a permutation of [0, grid), so the item set is unchanged.
 constexpr int kXcds = 8;
-constexpr int kXcdRun = 16;
+#ifndef CCM_XCD_RUN
+#define CCM_XCD_RUN 16
+#endif
+constexpr int kXcdRun = CCM_XCD_RUN;
 __device__ __forceinline__ int xcd_item(int b, int grid) {
   constexpr int span = kXcds * kXcdRun;
   const int full = grid / span * span;

@@ -143,6 +143,7 @@ struct Plan {
   int32_t n_sets = 0;
   std::vector<int32_t> seg_off;       // segment offsets of the order sort
   int64_t n_ord = 0;                  // n_sets * N
+  int32_t kd_levels = 0;              // k-d refinement levels (0: none)
   size_t sort_temp = 0;
   std::vector<SampleJob> sample;
   int64_t n_lib = 0;
@@ -193,14 +194,24 @@ struct Plan {
 bool use_table(const Plan& p, int E, int64_t ne, int64_t le);
 int64_t table_for(Plan& p, int64_t emb_off, int64_t ne, int E);
 
-// The key of an order set: dims and lags as in OrderJob.
+// The key of an order set: dims and lags as in OrderJob; kd_E > 0 asks for
+// the k-d refinement over the E coordinates of the embedding the set is
+// attached to (attach_kd).
 struct OrderKey {
   int32_t dims;
   int32_t lag[4];
+  int32_t kd_E = 0;
 };
 // Visiting order of the embedding of dimension E with delay tau: the value
-// order for E = 1, a Hilbert curve over the two oldest lag coordinates else.
+// order for E = 1, a Hilbert curve over the two coordinates for E = 2, and
+// from E = 3 a k-d order over all E coordinates (one set per embedding).
 OrderKey embedding_order(int32_t E, int32_t tau);
+// The embedding (at emb_off, n_e points) whose coordinates refine the order
+// set at key_off, when the set asks for a k-d refinement; also sets the
+// plan's number of refinement levels.
+void attach_kd(Plan& p, int64_t key_off, int32_t E, int64_t emb_off, int64_t ne);
+// hipcub's scratch for the plan's order sort.
+void size_order_sort(Plan& p);
 // E-sweep sharing: visiting order of E_max's common points, keyed on the
 // newest lag coordinates (the ones every E of the sweep uses): the two
 // newest, or for E_max >= 8 (where the long lists of the large E dominate)

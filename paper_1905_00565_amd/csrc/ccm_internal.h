@@ -36,12 +36,23 @@ struct IngestJob {
 //              S[i + lag[d]], each scaled to 32 / dims bits.
 // An index whose lags run past the series sorts last (it is never an
 // embedded point of an embedding that uses the set).
+//
+// A set with kd_E > 0 belongs to one embedding (kd_E coordinates, kd_n_e
+// points at kd_emb_off): after the sort above (dims == 1 on its newest lag
+// coordinate, so its first kd_n_e entries are the embedded points), its
+// order is refined into a k-d order -- the points are split at the median of
+// their widest coordinate, the halves again, for kd_levels levels -- so that
+// points close in all E coordinates are close in the order.
 struct OrderJob {
   int64_t src_off;   // floats into the FP32 series pool
   int64_t key_off;   // uint32 keys (and the sorted order) of this set
   int64_t n;         // series length
   int32_t dims;
   int32_t lag[4];
+  int32_t kd_E;      // 0: no k-d refinement
+  int64_t kd_emb_off;  // floats into the embedding pool
+  int64_t kd_n_e;
+  int32_t kd_levels; // levels of this set's refinement (from its n_e alone)
   int32_t pad;
 };
 
@@ -250,6 +261,15 @@ hipError_t sort_series(void* temp, size_t& temp_bytes, const uint32_t* keys_in,
                        uint32_t* keys_out, const int32_t* idx_in, int32_t* idx_out,
                        int64_t n_series, int32_t segs, const int32_t* seg_offsets,
                        hipStream_t st);
+
+// k-d refinement of the order sets with kd_E > 0 (see OrderJob), on the
+// order pool of n_sets segments of n_series entries: `order` holds the
+// sorted sets on entry and the refined ones on return; alt (the size of the
+// pool) is scratch.  Only kernels of this library run (no library sort: the
+// sequence is captured in graphs and replayed).
+hipError_t refine_orders_kd(const OrderJob* orders, int32_t n_sets, int levels,
+                            int64_t n_series, const float* emb, int32_t* order, int32_t* alt,
+                            hipStream_t st);
 
 // Largest embedding whose membership bitmask fits the gather kernel's LDS.
 int64_t gather_max_sorted_n_e();

@@ -187,6 +187,133 @@ __global__ __launch_bounds__(256) void k_order_keys(const OrderJob* __restrict__
   }
 }
 
+// Smallest and largest value over the 256 threads of a workgroup (every
+// thread gets both).
+__device__ __forceinline__ void block_minmax(float& lo, float& hi, float* s_lo, float* s_hi) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, o, 64));
+    hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+  }
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[wave] = lo;
+    s_hi[wave] = hi;
+  }
+  __syncthreads();
+  lo = fminf(fminf(s_lo[0], s_lo[1]), fminf(s_lo[2], s_lo[3]));
+  hi = fmaxf(fmaxf(s_hi[0], s_hi[1]), fmaxf(s_hi[2], s_hi[3]));
+}
+
+// One level of the k-d refinement (see OrderJob): workgroup (x, y) splits
+// node x of set y -- positions [lo, hi) = [x n_e / 2^level, (x+1) n_e /
+// 2^level) of the set's order -- at its median along the coordinate with the
+// widest range over the node (the first such coordinate on ties).  The h =
+// mid - lo smallest (coordinate, position) entries go to [lo, mid), the rest
+// to [mid, hi), each side in its input order, where mid = (2x+1) n_e /
+// 2^(level+1) is the next level's boundary between the node's halves.  The
+// h-th smallest coordinate T is found by a radix select on its ordered bits
+// (four 8-bit passes, histograms in LDS); the entries below T and the first
+// ones equal to T make up the lower half.  Sets set0 + blockIdx.y.  Input
+// `order`, output `out` (the
+// caller has copied every entry to out first, so nodes that do not split
+// keep their entries).
+__global__ __launch_bounds__(kBlock) void k_kd_split(const OrderJob* __restrict__ orders,
+                                                     int set0, int level,
+                                                     const float* __restrict__ emb,
+                                                     const int32_t* __restrict__ order,
+                                                     int32_t* __restrict__ out) {
+  __shared__ float s_lo[4], s_hi[4];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t s_pick[2];
+  __shared__ int s_wave[2][kBlock / 64];
+  const OrderJob J = orders[set0 + (int)blockIdx.y];
+  if (J.kd_E <= 0 || level >= J.kd_levels) return;
+  const int E = J.kd_E;
+  const int64_t x = blockIdx.x;
+  const int64_t lo = (x * J.kd_n_e) >> level;
+  const int64_t hi = ((x + 1) * J.kd_n_e) >> level;
+  const int64_t mid = ((2 * x + 1) * J.kd_n_e) >> (level + 1);
+  const int64_t h = mid - lo;                       // entries of the lower half
+  if (h <= 0 || h >= hi - lo) return;               // nothing moves
+  const float* __restrict__ e = emb + J.kd_emb_off;
+  const int32_t* __restrict__ o = order + J.key_off;
+  int32_t* __restrict__ w = out + J.key_off;
+  const int tid = threadIdx.x;
+
+  // the widest coordinate
+  int d = 0;
+  float width = -1.f;
+  for (int k = 0; k < E; ++k) {
+    float mn = __builtin_inff(), mx = -__builtin_inff();
+    for (int64_t p = lo + tid; p < hi; p += kBlock) {
+      const float v = e[(int64_t)o[p] * E + k];
+      mn = fminf(mn, v);
+      mx = fmaxf(mx, v);
+    }
+    block_minmax(mn, mx, s_lo, s_hi);
+    if (mx - mn > width) {
+      width = mx - mn;
+      d = k;
+    }
+  }
+
+  // radix select of the key of rank h - 1 (0-based)
+  uint32_t prefix = 0u, mask = 0u;
+  uint32_t rank = (uint32_t)(h - 1);
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hist[tid] = 0u;
+    __syncthreads();
+    for (int64_t p = lo + tid; p < hi; p += kBlock) {
+      const uint32_t key = ordered_bits(e[(int64_t)o[p] * E + d]);
+      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t cum = 0u, b = 0u;
+      for (; b < 255u && cum + hist[b] <= rank; ++b) cum += hist[b];
+      s_pick[0] = b;
+      s_pick[1] = rank - cum;
+    }
+    __syncthreads();
+    prefix |= s_pick[0] << shift;
+    mask |= 255u << shift;
+    rank = s_pick[1];
+    __syncthreads();
+  }
+  const uint32_t T = prefix;
+  const int64_t eq_left = (int64_t)rank + 1;      // entries equal to T in the lower half
+
+  // stable partition, 256 entries at a time
+  int64_t at_lo = lo, at_hi = mid, eq_seen = 0;
+  for (int64_t base = lo; base < hi; base += kBlock) {
+    const int64_t p = base + tid;
+    const bool valid = p < hi;
+    const int32_t idx = valid ? o[p] : 0;
+    const uint32_t key = valid ? ordered_bits(e[(int64_t)idx * E + d]) : 0u;
+    const bool is_eq = valid && key == T;
+    int n_eq;
+    const int r_eq = block_rank(is_eq, s_wave[0], n_eq);
+    const bool left = valid && (key < T || (is_eq && eq_seen + r_eq < eq_left));
+    int n_left;
+    const int r_left = block_rank(left, s_wave[1], n_left);
+    if (left) w[at_lo + r_left] = idx;
+    else if (valid) w[at_hi + (tid - r_left)] = idx;
+    const int64_t n_valid = hi - base < kBlock ? hi - base : kBlock;
+    at_lo += n_left;
+    at_hi += n_valid - n_left;
+    eq_seen += n_eq;
+  }
+}
+
+__global__ void k_copy_int(const int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                           int64_t n) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+       x += (int64_t)gridDim.x * blockDim.x)
+    dst[x] = src[x];
+}
+
 // Embedded points in visiting order: the order set restricted to indices
 // below n_e.  One workgroup per embedding.
 __global__ __launch_bounds__(kBlock) void k_query_order(
@@ -459,6 +586,30 @@ hipError_t launch_query_order(const EmbedJob* jobs, int n_jobs,
   k_query_order<<<n_jobs, kBlock, 0, st>>>(jobs, order, qord);
   return hipGetLastError();
 }
+
+hipError_t refine_orders_kd(const OrderJob* orders, int32_t n_sets, int levels,
+                            int64_t n_series, const float* emb, int32_t* order, int32_t* alt,
+                            hipStream_t st) {
+  if (n_sets <= 0 || levels <= 0) return hipSuccess;
+  const int64_t n = n_series * n_sets;
+  int32_t* cur = order;
+  int32_t* nxt = alt;
+  for (int lv = 0; lv < levels; ++lv) {
+    k_copy_int<<<blocks_for(n, 256), 256, 0, st>>>(cur, nxt, n);
+    for (int32_t s0 = 0; s0 < n_sets; s0 += 65535) {
+      const unsigned ny = (unsigned)std::min<int32_t>(65535, n_sets - s0);
+      k_kd_split<<<dim3(1u << lv, ny), kBlock, 0, st>>>(orders, s0, lv, emb, cur, nxt);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  if (cur != order) k_copy_int<<<blocks_for(n, 256), 256, 0, st>>>(cur, order, n);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_sample(const SampleJob* jobs, int64_t n_jobs, int32_t* out,
                          hipStream_t st) {

@@ -9,7 +9,31 @@ namespace ccmh {
 
 OrderKey embedding_order(int32_t E, int32_t tau) {
   if (E == 1) return {1, {0, 0, 0, 0}};
-  return {2, {0, tau, 0, 0}};
+  if (E == 2) return {2, {0, tau, 0, 0}};
+  // sorted first on the newest coordinate, which puts exactly the embedded
+  // points (i < n_e) first; the k-d levels then reorder them
+  return {1, {(E - 1) * tau, 0, 0, 0}, E};
+}
+
+// Leaves of about this many points end the k-d refinement.
+constexpr int64_t kKdLeaf = 48;
+constexpr int kKdMaxLevels = 12;
+
+void attach_kd(Plan& p, int64_t key_off, int32_t E, int64_t emb_off, int64_t ne) {
+  OrderJob& o = p.orders[(size_t)(key_off / p.spec.N)];
+  if (o.kd_E == 0) return;
+  o.kd_emb_off = emb_off;
+  o.kd_n_e = ne;
+  int lv = 1;
+  while (lv < kKdMaxLevels && (ne >> lv) > kKdLeaf) ++lv;
+  o.kd_levels = lv;
+  p.kd_levels = std::max(p.kd_levels, lv);
+  (void)E;
+}
+
+void size_order_sort(Plan& p) {
+  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, p.spec.N,
+                     p.n_sets, nullptr, nullptr));
 }
 
 OrderKey shared_order(int32_t Emax, int32_t tau) {
@@ -22,7 +46,7 @@ int64_t order_set(Plan& p, int series, const OrderKey& key) {
   const int64_t N = p.spec.N;
   for (size_t k = 0; k < p.orders.size(); ++k) {
     const OrderJob& o = p.orders[k];
-    if (o.src_off == series * N && o.dims == key.dims &&
+    if (o.src_off == series * N && o.dims == key.dims && o.kd_E == key.kd_E &&
         std::equal(key.lag, key.lag + 4, o.lag))
       return o.key_off;
   }
@@ -33,6 +57,7 @@ int64_t order_set(Plan& p, int series, const OrderKey& key) {
   o.n = N;
   o.dims = key.dims;
   for (int d = 0; d < 4; ++d) o.lag[d] = key.lag[d];
+  o.kd_E = key.kd_E;
   p.orders.push_back(o);
   p.n_sets = (int32_t)p.orders.size();
   p.n_ord = p.n_sets * N;
@@ -309,6 +334,7 @@ static Plan make_plan_nested(const Spec& s) {
         qord_off[sr] = p.n_qord;
         ord_off[sr] = order_set(p, sr, embedding_order(E, tau));
         p.embed.push_back({sr * N, p.n_emb, ord_off[sr], p.n_qord, ne, N, E, tau});
+        attach_kd(p, ord_off[sr], E, emb_off[sr], ne);
         p.n_emb += ne * E;
         p.n_qord += ne;
         p.max_embed = std::max(p.max_embed, ne * E);
@@ -394,8 +420,7 @@ static Plan make_plan_nested(const Spec& s) {
   p.n_rho = (int64_t)p.rz_fin.size();
   if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
   order_items(p);
-  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
-                     p.n_sets, nullptr, nullptr));
+  size_order_sort(p);
   p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
                    p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
                    (size_t)p.n_ord * 16 + p.n_scratch * 4 + p.segs.size() * 4 +
@@ -512,8 +537,7 @@ static Plan make_plan_shared(const Spec& s) {
   p.n_rho = (int64_t)p.rz_fin.size();
   if (p.rz.size() > (size_t)INT32_MAX) fail(CCM_E_INVAL, "too many realizations");
   order_items(p);
-  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
-                     p.n_sets, nullptr, nullptr));
+  size_order_sort(p);
   p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
                    p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
                    (size_t)p.n_ord * 16 + p.n_slots * sizeof(Moments) + p.n_out * 8 +
@@ -573,6 +597,7 @@ Plan make_plan(const Spec& s) {
         qord_off[sr] = p.n_qord;
         ord_off[sr] = order_set(p, sr, embedding_order(E, tau));
         p.embed.push_back({sr * N, p.n_emb, ord_off[sr], p.n_qord, ne, N, E, tau});
+        attach_kd(p, ord_off[sr], E, emb_off[sr], ne);
         p.n_emb += ne * E;
         p.n_qord += ne;
         p.max_embed = std::max(p.max_embed, ne * E);
@@ -650,8 +675,7 @@ Plan make_plan(const Spec& s) {
 
   order_items(p);
 
-  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
-                     p.n_sets, nullptr, nullptr));
+  size_order_sort(p);
   p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_emb * 4 + p.n_lib * 4 + p.n_pts * 4 +
                    p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +
                    (size_t)p.n_ord * 16 + p.n_table * 4 + p.tables.size() * sizeof(TableJob) +
@@ -703,6 +727,7 @@ Plan make_plan_matrix(const Spec& s) {
     qord_off[a] = p.n_qord;
     ord_off[a] = order_set(p, a, embedding_order(E, tau));
     p.embed.push_back({a * N, p.n_emb, ord_off[a], p.n_qord, ne, N, E, tau});
+    attach_kd(p, ord_off[a], E, emb_off[a], ne);
     p.n_emb += ne * E;
     p.n_qord += ne;
     p.max_embed = std::max(p.max_embed, ne * E);
@@ -774,8 +799,7 @@ Plan make_plan_matrix(const Spec& s) {
       }
   p.n_rho = (int64_t)p.rz.size() * (M - 1);
   order_items(p);
-  HIPCHK(sort_series(nullptr, p.sort_temp, nullptr, nullptr, nullptr, nullptr, N,
-                     p.n_sets, nullptr, nullptr));
+  size_order_sort(p);
   p.device_bytes = p.n64 * 8 + p.n32 * 4 + p.n_ord * 16 + p.n_emb * 4 + p.n_lib * 4 +
                    p.n_pts * 4 +
                    p.n_pj * 4 + p.n_qord * 4 + p.n_slots * 4 * kWaves + p.sort_temp +

@@ -198,6 +198,9 @@ void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
     size_t tb = p.sort_temp;
     HIPCHK(sort_series(b.sort_temp, tb, b.keys, b.keys_out, b.iota, b.order, p.spec.N,
                        p.n_sets, b.segoff, st));
+    if (p.kd_levels > 0)
+      HIPCHK(refine_orders_kd(b.orders, p.n_sets, p.kd_levels, p.spec.N, b.emb, b.order, b.iota,
+                              st));
   }
   HIPCHK(launch_query_order(b.embed, (int)p.embed.size(), b.order, b.qord, st));
   for (int E = 1; E <= kMaxE; ++E)
@@ -574,17 +577,16 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
         d_gather, d_partial, d_out, d_nbr, d_d2, d_pred, d_iota, d_keys, d_keys_out, d_order,
         d_segoff, d_temp, d_qord, d_start, d_orders;
     std::vector<int32_t> seg{0, (int32_t)N};
-    std::vector<OrderJob> oj(1);
+    // the same visiting order as the batched plans
+    Plan op;
+    op.spec.N = N;
     {
-      const OrderKey key = embedding_order(E, tau);
-      oj[0] = OrderJob{};
-      oj[0].n = N;
-      oj[0].dims = key.dims;
-      for (int d = 0; d < 4; ++d) oj[0].lag[d] = key.lag[d];
+      const int64_t ko = order_set(op, 0, embedding_order(E, tau));
+      attach_kd(op, ko, E, 0, ne);
+      size_order_sort(op);
     }
-    size_t temp_bytes = 0;
-    HIPCHK(sort_series(nullptr, temp_bytes, nullptr, nullptr, nullptr, nullptr, N, 1,
-                       nullptr, nullptr));
+    const std::vector<OrderJob>& oj = op.orders;
+    size_t temp_bytes = op.sort_temp;
     std::vector<IngestJob> ij{{0, 0, N}};
     std::vector<EmbedJob> ej{{0, 0, 0, 0, ne, N, E, tau}};
     GatherJob g{};
@@ -664,6 +666,9 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
     HIPCHK(sort_series(d_temp.p, temp_bytes, d_keys.as<uint32_t>(), d_keys_out.as<uint32_t>(),
                        d_iota.as<int32_t>(), d_order.as<int32_t>(), N, 1,
                        d_segoff.as<int32_t>(), st));
+    if (op.kd_levels > 0)
+      HIPCHK(refine_orders_kd(d_orders.as<OrderJob>(), 1, op.kd_levels, N, d_emb.as<float>(),
+                              d_order.as<int32_t>(), d_iota.as<int32_t>(), st));
     HIPCHK(launch_query_order(d_embed.as<EmbedJob>(), 1, d_order.as<int32_t>(),
                               d_qord.as<int32_t>(), st));
     HIPCHK(launch_gather(d_gather.as<GatherJob>(), 1, sorted ? ne : 0, d_emb.as<float>(),

@@ -317,6 +317,10 @@ void start_job(ccm_server* s, Job& j) {
                      at<uint32_t>(s, R0 + L.keys_out), at<int32_t>(s, R0 + L.iota),
                      at<int32_t>(s, R0 + L.order), N, p.n_sets,
                      at<int32_t>(s, R0 + L.d_segoff), st));
+  if (p.kd_levels > 0)
+    HIPCHK(refine_orders_kd(at<OrderJob>(s, R0 + L.d_orders), p.n_sets, p.kd_levels, N,
+                            at<float>(s, R0 + L.emb), at<int32_t>(s, R0 + L.order),
+                            at<int32_t>(s, R0 + L.iota), st));
   HIPCHK(launch_query_order(at<EmbedJob>(s, R0 + L.d_embed), (int)p.embed.size(),
                             at<int32_t>(s, R0 + L.order), at<int32_t>(s, R0 + L.qord), st));
   HIPCHK(launch_sample(at<SampleJob>(s, R0 + L.d_sample), (int64_t)p.sample.size(),

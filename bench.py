@@ -101,6 +101,10 @@ def parse():
     ap.add_argument("--workloads", type=int, default=1,
                     help="1: also time the small, long-series and causal-matrix "
                          "workloads and the elasticity study (0: skip)")
+    ap.add_argument("--legs", type=str,
+                    default="small,long,matrix,elasticity,index_table,nested,shared_e,forms",
+                    help="legs run with --workloads 1 (matrix-alone: the causal matrix "
+                         "without its plain comparison, for profiling)")
     ap.add_argument("--serve-jobs", type=int, default=200,
                     help="jobs per load point of the served leg (0: skip it)")
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95",
@@ -229,7 +233,7 @@ def _leg(ctx, torch, name, fn, reps, plain_fn=None, plain_reps=1, plain_note=Non
     return out
 
 
-def workloads_leg(ctx, torch, dev, stream):
+def workloads_leg(ctx, torch, dev, stream, which=("small", "long", "matrix")):
     """The other configurations of the method on one GPU: the small coupled
     map (launch-bound), the long noisy series, and the 64-series causal
     matrix (one neighbour search per library series shared by its 63
@@ -238,23 +242,27 @@ def workloads_leg(ctx, torch, dev, stream):
     res = {}
     f64 = dict(dtype=torch.float64, device=dev)
 
-    w = synth.workload_small()
-    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
-    a, b = torch.empty((len(w.L), w.r), **f64), torch.empty((len(w.L), w.r), **f64)
+    if "small" in which:
+        w = synth.workload_small()
+        X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+        a, b = torch.empty((len(w.L), w.r), **f64), torch.empty((len(w.L), w.r), **f64)
 
-    def small(flags=0):
-        return lambda: ctx.ccm_dev(X, Y, w.E[0], w.tau[0], w.L, w.r, w.seed, a, b,
-                                   stream=stream, flags=flags)
-    res["small"] = _leg(ctx, torch, w.name, small(), 20,
-                        (small(), small(capi.CCM_FLAG_PLAIN)), 3, "the whole workload")
+        def small(flags=0):
+            return lambda: ctx.ccm_dev(X, Y, w.E[0], w.tau[0], w.L, w.r, w.seed, a, b,
+                                       stream=stream, flags=flags)
+        res["small"] = _leg(ctx, torch, w.name, small(), 20,
+                            (small(), small(capi.CCM_FLAG_PLAIN)), 3, "the whole workload")
 
-    w = synth.workload_long()
-    X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
-    a, b = torch.empty((len(w.L), w.r), **f64), torch.empty((len(w.L), w.r), **f64)
-    res["long"] = _leg(ctx, torch, w.name,
-                       lambda: ctx.ccm_dev(X, Y, w.E[0], w.tau[0], w.L, w.r, w.seed, a, b,
-                                           stream=stream), 1)
+    if "long" in which:
+        w = synth.workload_long()
+        X, Y = torch.tensor(w.X, device=dev), torch.tensor(w.Y, device=dev)
+        a, b = torch.empty((len(w.L), w.r), **f64), torch.empty((len(w.L), w.r), **f64)
+        res["long"] = _leg(ctx, torch, w.name,
+                           lambda: ctx.ccm_dev(X, Y, w.E[0], w.tau[0], w.L, w.r, w.seed, a, b,
+                                               stream=stream), 1)
 
+    if "matrix" not in which:
+        return res
     m = synth.workload_matrix()
     S = torch.tensor(m["S"], device=dev)
     M = S.shape[0]
@@ -264,8 +272,9 @@ def workloads_leg(ctx, torch, dev, stream):
     def matrix(r, out, flags=0):
         return lambda: ctx.ccm_matrix_dev(S, m["E"], m["tau"], m["L"], r, m["seed"], out,
                                           stream=stream, flags=flags)
-    res["matrix"] = _leg(ctx, torch, m["name"], matrix(m["r"], rho), 1,
-                         (matrix(1, rho1), matrix(1, rho1, capi.CCM_FLAG_PLAIN)), 1,
+    plain = None if "matrix-alone" in which else (matrix(1, rho1),
+                                                     matrix(1, rho1, capi.CCM_FLAG_PLAIN))
+    res["matrix"] = _leg(ctx, torch, m["name"], matrix(m["r"], rho), 1, plain, 1,
                          "r = 1 (640 neighbour searches, 40 320 rho values)")
     return res
 
@@ -669,13 +678,23 @@ def main():
         },
     }
     if a.workloads:
+        legs = set(v for v in a.legs.split(",") if v)
+        if "matrix-alone" in legs:
+            legs.add("matrix")
         print("bench: other workloads and the elasticity study", file=sys.stderr, flush=True)
-        out["workloads"] = workloads_leg(ctx, torch, dev, stream)
-        out["elasticity"] = elasticity_leg(ctx, torch, dev, stream)
-        out["index_table"] = table_leg(ctx, torch, dev, stream)
-        out["nested"] = nested_leg(ctx, torch, dev, stream)
-        out["shared_e"] = shared_e_leg(ctx, torch, dev, stream, out["ms_per_step"])
-        out["forms"] = forms_leg(ctx, torch, dev, stream, out["ms_per_step"])
+        which = tuple(k for k in ("small", "long", "matrix", "matrix-alone") if k in legs)
+        if which:
+            out["workloads"] = workloads_leg(ctx, torch, dev, stream, which)
+        if "elasticity" in legs:
+            out["elasticity"] = elasticity_leg(ctx, torch, dev, stream)
+        if "index_table" in legs:
+            out["index_table"] = table_leg(ctx, torch, dev, stream)
+        if "nested" in legs:
+            out["nested"] = nested_leg(ctx, torch, dev, stream)
+        if "shared_e" in legs:
+            out["shared_e"] = shared_e_leg(ctx, torch, dev, stream, out["ms_per_step"])
+        if "forms" in legs:
+            out["forms"] = forms_leg(ctx, torch, dev, stream, out["ms_per_step"])
     if a.serve_jobs > 0:
         print(f"bench: served leg, {a.serve_jobs} jobs per load", file=sys.stderr, flush=True)
         ctx.profile_enable(False)

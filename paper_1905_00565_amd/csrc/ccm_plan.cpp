@@ -9,14 +9,20 @@ namespace ccmh {
 
 OrderKey embedding_order(int32_t E, int32_t tau) {
   if (E == 1) return {1, {0, 0, 0, 0}};
-  if (E == 2) return {2, {0, tau, 0, 0}};
+#ifndef CCM_KD_MIN_E
+#define CCM_KD_MIN_E 3
+#endif
+  if (E < CCM_KD_MIN_E) return {2, {0, tau, 0, 0}};
   // sorted first on the newest coordinate, which puts exactly the embedded
   // points (i < n_e) first; the k-d levels then reorder them
   return {1, {(E - 1) * tau, 0, 0, 0}, E};
 }
 
 // Leaves of about this many points end the k-d refinement.
-constexpr int64_t kKdLeaf = 48;
+#ifndef CCM_KD_LEAF
+#define CCM_KD_LEAF 48
+#endif
+constexpr int64_t kKdLeaf = CCM_KD_LEAF;
 constexpr int kKdMaxLevels = 12;
 
 void attach_kd(Plan& p, int64_t key_off, int32_t E, int64_t emb_off, int64_t ne) {

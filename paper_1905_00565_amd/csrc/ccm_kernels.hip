@@ -353,10 +353,26 @@ __device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
 // a library is keyed by (seed, E, tau, L_eff, r) folded through the mix.
 // Once every remaining candidate is needed the rest are taken without draws:
 // the test would accept each of them whatever the draw.
-__global__ void k_sample(const SampleJob* __restrict__ jobs, int64_t n_jobs,
-                         int32_t* __restrict__ out_pool) {
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= n_jobs) return;
+//
+// One wavefront per library.  The stream's state advances by the same
+// constant for every candidate visited, so candidate j's draw is the output
+// mix of (keyed state + (j+1) gamma): the 64 lanes form the draws and their
+// integers u_j below (n_e - j) of 64 consecutive candidates at once.  The
+// decisions depend on how many were taken before (t_j = needed before j;
+// take j when u_j < t_j), but within 64 candidates t_j is at most 63 below
+// the step's t_0: u_j < t_0 - 63 is taken and u_j >= t_0 is not whatever
+// came before, and only the lanes in between are decided one after another,
+// in candidate order, with the count of takes below them.  Then t_j is known
+// for every lane, and the first j with t_j = n_e - j (every remaining one
+// needed) takes the rest.  Each u_j is below n_e < 2^31.
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+
+__global__ __launch_bounds__(256) void k_sample(const SampleJob* __restrict__ jobs,
+                                                int64_t n_jobs,
+                                                int32_t* __restrict__ out_pool) {
+  const int lane = threadIdx.x & 63;
+  const int64_t id = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (id >= n_jobs) return;                       // the whole wavefront
   const SampleJob J = jobs[id];
   uint64_t st = 0;
   st = sm_mix(st ^ J.seed);
@@ -365,16 +381,41 @@ __global__ void k_sample(const SampleJob* __restrict__ jobs, int64_t n_jobs,
   st = sm_mix(st ^ (uint64_t)J.l_eff);
   st = sm_mix(st ^ (uint64_t)(int64_t)J.r_index);
   int32_t* __restrict__ out = out_pool + J.out_off;
-  int64_t s = 0;
-  int64_t j = 0;
-  for (; j < J.n_e && s < J.l_eff; ++j) {
-    if (J.l_eff - s == J.n_e - j) break;        // all the rest are needed
-    st += 0x9e3779b97f4a7c15ull;
-    const uint64_t z = sm_mix(st);
-    const uint64_t u = __umul64hi(z, (uint64_t)(J.n_e - j));
-    if (u < (uint64_t)(J.l_eff - s)) out[s++] = (int32_t)j;
+  const int64_t ne = J.n_e, le = J.l_eff;
+  const uint64_t below_lane = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int64_t s = 0;                                  // taken so far
+  for (int64_t j0 = 0; s < le && j0 < ne; j0 += 64) {
+    const int64_t j = j0 + lane;
+    const bool valid = j < ne;
+    int64_t u = 0;
+    if (valid)
+      u = (int64_t)__umul64hi(sm_mix(st + (uint64_t)(j + 1) * kGamma), (uint64_t)(ne - j));
+    const int64_t t0 = le - s;
+    uint64_t take = __builtin_amdgcn_ballot_w64(valid && u + 63 < t0);
+    uint64_t open = __builtin_amdgcn_ballot_w64(valid && u + 63 >= t0 && u < t0);
+    while (open) {                                // in candidate order
+      const int l = __builtin_ctzll(open);
+      open &= open - 1ull;
+      const int64_t tl = t0 - __popcll(take & ((1ull << l) - 1ull));
+      const int64_t ul = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)u, l);
+      if (ul < tl) take |= 1ull << l;
+    }
+    // the first candidate from which every remaining one is needed
+    const int64_t tj = t0 - __popcll(take & below_lane);
+    const uint64_t full = __builtin_amdgcn_ballot_w64(valid && tj == ne - j);
+    int64_t rest = -1;
+    if (full) {
+      const int l = __builtin_ctzll(full);
+      rest = j0 + l;
+      take &= (1ull << l) - 1ull;
+    }
+    if ((take >> lane) & 1ull) out[s + __popcll(take & below_lane)] = (int32_t)j;
+    s += __popcll(take);
+    if (rest >= 0) {
+      for (int64_t k = lane; k < le - s; k += 64) out[s + k] = (int32_t)(rest + k);
+      s = le;
+    }
   }
-  for (; s < J.l_eff; ++s, ++j) out[s] = (int32_t)j;
 }
 
 // Nested libraries (an option of this library): the first n_out points of
@@ -398,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_nested(const NestedJob* __res
   st = sm_mix(st ^ (uint64_t)(int64_t)J.r_index);
   int32_t* __restrict__ out = out_pool + J.out_off;
   for (int64_t k = 0; k < J.n_out; ++k) {
-    st += 0x9e3779b97f4a7c15ull;
+    st += kGamma;
     const uint64_t z = sm_mix(st);
     const int64_t j = k + (int64_t)__umul64hi(z, (uint64_t)(J.n_e - k));
     const int32_t t = a[k];
@@ -614,8 +655,8 @@ hipError_t refine_orders_kd(const OrderJob* orders, int32_t n_sets, int levels,
 hipError_t launch_sample(const SampleJob* jobs, int64_t n_jobs, int32_t* out,
                          hipStream_t st) {
   if (n_jobs <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((n_jobs + 63) / 64);
-  k_sample<<<blocks, 64, 0, st>>>(jobs, n_jobs, out);
+  const unsigned blocks = (unsigned)((n_jobs + 3) / 4);   // one wavefront per library
+  k_sample<<<blocks, 256, 0, st>>>(jobs, n_jobs, out);
   return hipGetLastError();
 }
 

@@ -43,7 +43,17 @@ def rho_close(a, b, tol=TOL):
 
 def test_sampler_bit_exact(ctx, orc):
     keys = [(1, 2, 1, 100, 0, 999), (2, 10, 5, 7848, 249, 9955), (3, 3, 2, 50000, 17, 99996),
-            (12345678901234, 1, 1, 5, 3, 7), (5, 4, 1, 19997, 99, 19997), (9, 7, 3, 2, 1, 3)]
+            (12345678901234, 1, 1, 5, 3, 7), (5, 4, 1, 19997, 99, 19997), (9, 7, 3, 2, 1, 3),
+            # one candidate; chunk edges of the sampler's 64-candidate steps; all taken
+            (7, 2, 1, 1, 0, 1), (7, 2, 1, 1, 0, 64), (7, 2, 1, 63, 0, 64), (7, 2, 1, 64, 5, 65),
+            (8, 3, 2, 127, 4, 128), (8, 3, 2, 3, 4, 129), (2**63 + 5, 5, 4, 300, 7, 1000),
+            (11, 6, 2, 5000, 3, 5000)]
+    rng = np.random.default_rng(77)
+    for _ in range(40):
+        ne = int(rng.integers(1, 20000))
+        keys.append((int(rng.integers(0, 2**63)), int(rng.integers(1, 11)),
+                     int(rng.integers(1, 6)), int(rng.integers(1, ne + 1)),
+                     int(rng.integers(0, 300)), ne))
     for seed, E, tau, le, ri, ne in keys:
         g = ctx.ccm_library(ne, E, tau, le, ri, seed)
         o = orc.sample_library(seed, E, tau, le, ri, ne)

@@ -264,12 +264,12 @@ hipError_t sort_series(void* temp, size_t& temp_bytes, const uint32_t* keys_in,
 
 // k-d refinement of the order sets with kd_E > 0 (see OrderJob), on the
 // order pool of n_sets segments of n_series entries: `order` holds the
-// sorted sets on entry and the refined ones on return; alt (the size of the
-// pool) is scratch.  Only kernels of this library run (no library sort: the
-// sequence is captured in graphs and replayed).
+// sorted sets on entry and the refined ones on return; alt and keys (the
+// size of the pool) are scratch.  Only kernels of this library run (no
+// library sort: the sequence is captured in graphs and replayed).
 hipError_t refine_orders_kd(const OrderJob* orders, int32_t n_sets, int levels,
                             int64_t n_series, const float* emb, int32_t* order, int32_t* alt,
-                            hipStream_t st);
+                            uint32_t* keys, hipStream_t st);
 
 // Largest embedding whose membership bitmask fits the gather kernel's LDS.
 int64_t gather_max_sorted_n_e();

@@ -215,7 +215,8 @@ __device__ __forceinline__ void block_minmax(float& lo, float& hi, float* s_lo, 
 // 2^(level+1) is the next level's boundary between the node's halves.  The
 // h-th smallest coordinate T is found by a radix select on its ordered bits
 // (four 8-bit passes, histograms in LDS); the entries below T and the first
-// ones equal to T make up the lower half.  Sets set0 + blockIdx.y.  Input
+// ones equal to T make up the lower half (the node's keys are formed once
+// into `keys`, scratch of the pool's size).  Sets set0 + blockIdx.y.  Input
 // `order`, output `out` (the
 // caller has copied every entry to out first, so nodes that do not split
 // keep their entries).
@@ -223,8 +224,9 @@ __global__ __launch_bounds__(kBlock) void k_kd_split(const OrderJob* __restrict_
                                                      int set0, int level,
                                                      const float* __restrict__ emb,
                                                      const int32_t* __restrict__ order,
+                                                     uint32_t* __restrict__ keys,
                                                      int32_t* __restrict__ out) {
-  __shared__ float s_lo[4], s_hi[4];
+  __shared__ float s_lo[kBlock / 64][kMaxE], s_hi[kBlock / 64][kMaxE];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t s_pick[2];
   __shared__ int s_wave[2][kBlock / 64];
@@ -242,31 +244,63 @@ __global__ __launch_bounds__(kBlock) void k_kd_split(const OrderJob* __restrict_
   int32_t* __restrict__ w = out + J.key_off;
   const int tid = threadIdx.x;
 
-  // the widest coordinate
+  // the widest coordinate: every coordinate's range in one pass
+  float mn[kMaxE], mx[kMaxE];
+#pragma unroll
+  for (int k = 0; k < kMaxE; ++k) {
+    mn[k] = __builtin_inff();
+    mx[k] = -__builtin_inff();
+  }
+  for (int64_t p = lo + tid; p < hi; p += kBlock) {
+    const float* __restrict__ v = e + (int64_t)o[p] * E;
+#pragma unroll
+    for (int k = 0; k < kMaxE; ++k)
+      if (k < E) {
+        mn[k] = fminf(mn[k], v[k]);
+        mx[k] = fmaxf(mx[k], v[k]);
+      }
+  }
+  const int wave = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < kMaxE; ++k) {
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) {
+      mn[k] = fminf(mn[k], __shfl_xor(mn[k], sh, 64));
+      mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], sh, 64));
+    }
+    if ((tid & 63) == 0) {
+      s_lo[wave][k] = mn[k];
+      s_hi[wave][k] = mx[k];
+    }
+  }
+  __syncthreads();
   int d = 0;
   float width = -1.f;
   for (int k = 0; k < E; ++k) {
-    float mn = __builtin_inff(), mx = -__builtin_inff();
-    for (int64_t p = lo + tid; p < hi; p += kBlock) {
-      const float v = e[(int64_t)o[p] * E + k];
-      mn = fminf(mn, v);
-      mx = fmaxf(mx, v);
+    float a = s_lo[0][k], b = s_hi[0][k];
+#pragma unroll
+    for (int wv = 1; wv < kBlock / 64; ++wv) {
+      a = fminf(a, s_lo[wv][k]);
+      b = fmaxf(b, s_hi[wv][k]);
     }
-    block_minmax(mn, mx, s_lo, s_hi);
-    if (mx - mn > width) {
-      width = mx - mn;
+    if (b - a > width) {
+      width = b - a;
       d = k;
     }
   }
+  // the node's keys, formed once (scratch of the order pool's size)
+  uint32_t* __restrict__ kc = keys + J.key_off;
+  for (int64_t p = lo + tid; p < hi; p += kBlock) kc[p] = ordered_bits(e[(int64_t)o[p] * E + d]);
 
-  // radix select of the key of rank h - 1 (0-based)
+  // radix select of the key of rank h - 1 (0-based); each thread reads the
+  // keys it wrote
   uint32_t prefix = 0u, mask = 0u;
   uint32_t rank = (uint32_t)(h - 1);
   for (int shift = 24; shift >= 0; shift -= 8) {
     hist[tid] = 0u;
     __syncthreads();
     for (int64_t p = lo + tid; p < hi; p += kBlock) {
-      const uint32_t key = ordered_bits(e[(int64_t)o[p] * E + d]);
+      const uint32_t key = kc[p];
       if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
     }
     __syncthreads();
@@ -291,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_kd_split(const OrderJob* __restrict_
     const int64_t p = base + tid;
     const bool valid = p < hi;
     const int32_t idx = valid ? o[p] : 0;
-    const uint32_t key = valid ? ordered_bits(e[(int64_t)idx * E + d]) : 0u;
+    const uint32_t key = valid ? kc[p] : 0u;
     const bool is_eq = valid && key == T;
     int n_eq;
     const int r_eq = block_rank(is_eq, s_wave[0], n_eq);
@@ -630,7 +664,7 @@ hipError_t launch_query_order(const EmbedJob* jobs, int n_jobs,
 
 hipError_t refine_orders_kd(const OrderJob* orders, int32_t n_sets, int levels,
                             int64_t n_series, const float* emb, int32_t* order, int32_t* alt,
-                            hipStream_t st) {
+                            uint32_t* keys, hipStream_t st) {
   if (n_sets <= 0 || levels <= 0) return hipSuccess;
   const int64_t n = n_series * n_sets;
   int32_t* cur = order;
@@ -639,7 +673,7 @@ hipError_t refine_orders_kd(const OrderJob* orders, int32_t n_sets, int levels,
     k_copy_int<<<blocks_for(n, 256), 256, 0, st>>>(cur, nxt, n);
     for (int32_t s0 = 0; s0 < n_sets; s0 += 65535) {
       const unsigned ny = (unsigned)std::min<int32_t>(65535, n_sets - s0);
-      k_kd_split<<<dim3(1u << lv, ny), kBlock, 0, st>>>(orders, s0, lv, emb, cur, nxt);
+      k_kd_split<<<dim3(1u << lv, ny), kBlock, 0, st>>>(orders, s0, lv, emb, cur, keys, nxt);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

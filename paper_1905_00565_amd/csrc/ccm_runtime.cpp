@@ -200,7 +200,7 @@ void enqueue_plan(ccm_ctx* c, const Plan& p, const PlanBuffers& b,
                        p.n_sets, b.segoff, st));
     if (p.kd_levels > 0)
       HIPCHK(refine_orders_kd(b.orders, p.n_sets, p.kd_levels, p.spec.N, b.emb, b.order, b.iota,
-                              st));
+                              b.keys, st));
   }
   HIPCHK(launch_query_order(b.embed, (int)p.embed.size(), b.order, b.qord, st));
   for (int E = 1; E <= kMaxE; ++E)
@@ -668,7 +668,8 @@ ccm_status ccm_neighbors(ccm_ctx* c, const double* lib_series, const double* tar
                        d_segoff.as<int32_t>(), st));
     if (op.kd_levels > 0)
       HIPCHK(refine_orders_kd(d_orders.as<OrderJob>(), 1, op.kd_levels, N, d_emb.as<float>(),
-                              d_order.as<int32_t>(), d_iota.as<int32_t>(), st));
+                              d_order.as<int32_t>(), d_iota.as<int32_t>(),
+                              d_keys.as<uint32_t>(), st));
     HIPCHK(launch_query_order(d_embed.as<EmbedJob>(), 1, d_order.as<int32_t>(),
                               d_qord.as<int32_t>(), st));
     HIPCHK(launch_gather(d_gather.as<GatherJob>(), 1, sorted ? ne : 0, d_emb.as<float>(),

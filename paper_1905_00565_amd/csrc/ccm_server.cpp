@@ -320,7 +320,7 @@ void start_job(ccm_server* s, Job& j) {
   if (p.kd_levels > 0)
     HIPCHK(refine_orders_kd(at<OrderJob>(s, R0 + L.d_orders), p.n_sets, p.kd_levels, N,
                             at<float>(s, R0 + L.emb), at<int32_t>(s, R0 + L.order),
-                            at<int32_t>(s, R0 + L.iota), st));
+                            at<int32_t>(s, R0 + L.iota), at<uint32_t>(s, R0 + L.keys), st));
   HIPCHK(launch_query_order(at<EmbedJob>(s, R0 + L.d_embed), (int)p.embed.size(),
                             at<int32_t>(s, R0 + L.order), at<int32_t>(s, R0 + L.qord), st));
   HIPCHK(launch_sample(at<SampleJob>(s, R0 + L.d_sample), (int64_t)p.sample.size(),

@@ -220,16 +220,20 @@ __device__ __forceinline__ void compute_chunk(
   }
 }
 
-// E = 1: d2 = fl(d * d) with d = fl(q - p) is a non-decreasing function of
-// |d|, so the smallest d2 of a group is fl(m * m) with m the smallest |d|:
-// the group check needs one subtraction and half a three-way minimum per
-// pair instead of a subtraction and a product.  A group that passes
-// recomputes its differences (the same values) and its exact d2.
-template <int Q, int MODE, int G>
-__device__ __forceinline__ void compute_chunk_e1(
-    const Chunk<1, G>& ch, const float (&qc)[Q][1], const int (&qi)[Q], int window,
-    double (&key)[Q][Slots<1, MODE>::KS]) {
-  constexpr int KS = Slots<1, MODE>::KS;
+// Small E: a cheaper group check with the same outcome.  Each step of the
+// binary32 chain adds a non-negative term, and rounding is monotone, so a
+// pair's d2 is at least fl(d_k * d_k) for every coordinate k, that is at least
+// fl(m * m) with m the largest |d_k|; a group none of whose candidates has
+// fl(m * m) <= the running (E+1)-th key has no candidate to insert.  The check
+// costs E subtractions, E-1 maxima and half a three-way minimum per pair (at
+// E = 1 the bound is d2 itself: fl(d * d) does not decrease with |d|); a group
+// that passes recomputes its exact d2 (the same values) and inserts as the
+// default check does.
+template <int E, int Q, int MODE, int G>
+__device__ __forceinline__ void compute_chunk_bound(
+    const Chunk<E, G>& ch, const float (&qc)[Q][E], const int (&qi)[Q], int window,
+    double (&key)[Q][Slots<E, MODE>::KS]) {
+  constexpr int KS = Slots<E, MODE>::KS;
   float a[Q];
 #pragma unroll
   for (int m = 0; m < Q; ++m) a[m] = __builtin_inff();
@@ -237,20 +241,21 @@ __device__ __forceinline__ void compute_chunk_e1(
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
-      float v = qc[m][0] - ch.p[g][0];
+      float v = fabsf(qc[m][0] - ch.p[g][0]);
+#pragma unroll
+      for (int k = 1; k < E; ++k) v = fmaxf(v, fabsf(qc[m][k] - ch.p[g][k]));
       if (MODE == kWindow) {
         const int dj = ch.j[g] - qi[m];
         if (dj <= window && dj >= -window) v = __builtin_nanf("");
       }
-      a[m] = fminf(a[m], fabsf(v));
+      a[m] = fminf(a[m], v);
     }
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
     if (__builtin_amdgcn_ballot_w64(a[m] * a[m] <= key_d2(key[m][KS - 1]))) {
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const float v = qc[m][0] - ch.p[g][0];
-        const float d2 = v * v;
+        const float d2 = sqdist<E>(qc[m], ch.p[g]);
         bool ok = d2 <= key_d2(key[m][KS - 1]);
         if (MODE == kExclSelf) ok = ok && ch.j[g] != qi[m];
         if (MODE == kWindow) {
@@ -267,8 +272,8 @@ template <int E, int Q, int MODE, int G>
 __device__ __forceinline__ void check_chunk(
     const Chunk<E, G>& ch, const float (&qc)[Q][E], const int (&qi)[Q], int window,
     double (&key)[Q][Slots<E, MODE>::KS]) {
-  if constexpr (E == 1)
-    compute_chunk_e1<Q, MODE, G>(ch, qc, qi, window, key);
+  if constexpr (kBoundCheck[E] != 0)
+    compute_chunk_bound<E, Q, MODE, G>(ch, qc, qi, window, key);
   else
     compute_chunk<E, Q, MODE, G>(ch, qc, qi, window, key);
 }

@@ -45,6 +45,12 @@
 #define CCM_NESTED_W {0, 7, 6, 4, 4, 4, 5, 4, 4, 4, 4}
 #endif
 
+// Group check per E (index E): 1 = the largest-coordinate bound (a cheaper
+// check with the same outcome), 0 = the exact distances of the group.
+#ifndef CCM_BOUND_CHECK
+#define CCM_BOUND_CHECK {0, 1, 0, 1, 0, 0, 0, 0, 0, 0, 0}
+#endif
+
 // Causal matrix: minimum wavefronts per SIMD of the many-target kernel (its
 // per-target stage holds more state than the plain scan's moments; 0: free).
 #ifndef CCM_MULTI_W
@@ -52,6 +58,7 @@
 #endif
 
 namespace ccmk {
+constexpr int kBoundCheck[11] = CCM_BOUND_CHECK;
 constexpr int kMultiW[11] = CCM_MULTI_W;
 constexpr int kNestedW[11] = CCM_NESTED_W;
 constexpr int kTuneQ[11] = CCM_TUNE_Q;

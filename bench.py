@@ -60,6 +60,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "crossmap_sweep_coupled_logistic_N10000_traffic.json")
 KERNEL_SOURCES = ["paper_1905_00565_amd/csrc/ccm_device.h",
                   "paper_1905_00565_amd/csrc/ccm_inst.hip",
+                  "paper_1905_00565_amd/csrc/ccm_inst_multi.hip",
                   "paper_1905_00565_amd/csrc/ccm_internal.h",
                   "paper_1905_00565_amd/csrc/ccm_tune.h"]
 

@@ -29,6 +29,10 @@ SOURCES = ["ccm_kernels.hip", "ccm_sort.hip", "ccm_noalloc.hip", "ccm_plan.cpp",
 # bulk of the build, so the ten compile in parallel).
 INST_SOURCE = "ccm_inst.hip"
 INST_E = tuple(range(1, 11))
+# The causal-matrix kernels, also once per E, without machine-level
+# loop-invariant hoisting (the unit's header says why).
+MULTI_SOURCE = "ccm_inst_multi.hip"
+MULTI_FLAGS = ("-mllvm", "-disable-machine-licm")
 
 
 def hipcc() -> str:
@@ -56,6 +60,8 @@ def units(defines=()):
     for e in INST_E:
         out.append((INST_SOURCE, os.path.join(BUILD, f"ccm_inst_e{e}.o"),
                     [f"-DCCM_INST_E={e}", *defines]))
+        out.append((MULTI_SOURCE, os.path.join(BUILD, f"ccm_inst_multi_e{e}.o"),
+                    [f"-DCCM_INST_E={e}", *MULTI_FLAGS, *defines]))
     return out
 
 

@@ -619,14 +619,14 @@ __device__ __forceinline__ void sums_init(Sums& su) {
   su.v[7] = su.v[9] = -__builtin_inf();
 }
 
+// One (observed, predicted) pair; the count is added per query set.
 __device__ __forceinline__ void sums_add(Sums& su, double o, double pred, double shift) {
   const double a = o - shift, p = pred - shift;
-  su.v[0] += 1.0;
   su.v[1] += a;
   su.v[2] += p;
-  su.v[3] += a * a;
-  su.v[4] += p * p;
-  su.v[5] += a * p;
+  su.v[3] = fma(a, a, su.v[3]);
+  su.v[4] = fma(p, p, su.v[4]);
+  su.v[5] = fma(a, p, su.v[5]);
   su.v[6] = fmin(su.v[6], o);
   su.v[7] = fmax(su.v[7], o);
   su.v[8] = fmin(su.v[8], pred);
@@ -641,10 +641,11 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // LDS of the many-target item: per wavefront, one query set's neighbours
-// (w double [K][64], row offsets nj*mp int32 [K][64], qi*mp int32 [64]);
-// reused afterwards for the wavefronts' per-target sums (Sums [kWaves][64]).
-// A row offset fits in int32: it is below N*mp <= M*N + N, and the planner
-// caps M*N at INT32_MAX/2.
+// (w double [K][64], row offsets nj*mp int32 [K][64], qi*mp int32 [64]; the
+// row-offset area first holds the squared distances' bits while the weights
+// are formed); reused afterwards for the wavefronts' per-target sums (Sums
+// [kWaves][64]).  A row offset fits in int32: it is below N*mp <= M*N + N,
+// and the planner caps M*N at INT32_MAX/2.
 template <int E>
 struct MultiLds {
   static constexpr int K = E + 1;
@@ -653,6 +654,36 @@ struct MultiLds {
   static constexpr int kRed = kWaves * 64 * (int)sizeof(Sums);
   static constexpr int kBytes = kStage > kRed ? kStage : kRed;
 };
+
+// The simplex weights of one query set, one neighbour at a time: the same
+// operations in the same order as simplex_weights (so the same bits), with a
+// single exp in flight (a smaller register peak after the scan).  Lane l's
+// squared distances are the float bits d2b[t*64 + l]; weight t goes to
+// w[t*64 + l].  The two areas are disjoint, so lanes that take different
+// branches cannot overwrite each other's inputs.
+template <int K>
+__device__ __forceinline__ void stage_weights(const int32_t* __restrict__ d2b,
+                                              double* __restrict__ w, int lane) {
+  const double d0 = sqrt((double)__int_as_float(d2b[lane]));
+  double su = 0.0;
+  if (d0 > 0.0) {
+#pragma unroll 1
+    for (int t = 0; t < K; ++t) {
+      const double u = exp(-sqrt((double)__int_as_float(d2b[t * 64 + lane])) / d0);
+      w[t * 64 + lane] = u;
+      su += u;
+    }
+  } else {
+#pragma unroll 1
+    for (int t = 0; t < K; ++t) {
+      const double u = __int_as_float(d2b[t * 64 + lane]) == 0.0f ? 1.0 : 0.0;
+      w[t * 64 + lane] = u;
+      su += u;
+    }
+  }
+#pragma unroll 1
+  for (int t = 0; t < K; ++t) w[t * 64 + lane] = w[t * 64 + lane] / su;
+}
 
 // One block of 64 targets of the many-target stage (see below): lane b of
 // each wavefront accumulates target b0 + b over the wavefront's queries, set
@@ -686,28 +717,27 @@ __device__ __forceinline__ void multi_target_block(const ScanState<E, Q, MODE>& 
     {
       float nd[K];
       int32_t nj[K];
-      double w[K];
       select_neighbors<E, Q, MODE>(S, m, nd, nj);
-      simplex_weights<K>(nd, w);
       sqrow[lane] = S.qi[m] * mp;
 #pragma unroll
-      for (int t = 0; t < K; ++t) {
-        srow[t * 64 + lane] = nj[t] * mp;
-        sw[t * 64 + lane] = w[t];
-      }
+      for (int t = 0; t < K; ++t) srow[t * 64 + lane] = __float_as_int(nd[t]);
+      stage_weights<K>(srow, sw, lane);
+#pragma unroll
+      for (int t = 0; t < K; ++t) srow[t * 64 + lane] = nj[t] * mp;
     }
     wave_sync();
     if (act) {
-      // one query per step, its K + 1 loads issued before any is used (two
-      // per step measured no faster)
+      su.v[0] += (double)nq;
+      // one query per step, its K + 1 loads issued before any is used;
+      // pred = w_0 v_0 + ... as a chain of fused multiply-adds
       for (int q = 0; q < nq; ++q) {
         double v[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) v[t] = Tb[srow[t * 64 + q]];
         const double o = Tb[sqrow[q]];
-        double pred = 0.0;
+        double pred = sw[q] * v[0];
 #pragma unroll
-        for (int t = 0; t < K; ++t) pred += sw[t * 64 + q] * v[t];
+        for (int t = 1; t < K; ++t) pred = fma(sw[t * 64 + q], v[t], pred);
         sums_add(su, o, pred, shift);
       }
     }

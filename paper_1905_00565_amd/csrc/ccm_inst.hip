@@ -2,8 +2,9 @@
 // this file once per E = 1..10 with -DCCM_INST_E=E, so the instances of the
 // ten dimensions compile in parallel; each object holds the cross-map
 // (plain, test-hook and table variants of every exclusion mode), the
-// causal-matrix, nested-library, E-sweep-sharing (E_max = E) and
-// table-build kernels of its E, and their launchers.
+// nested-library, E-sweep-sharing (E_max = E) and table-build kernels of its
+// E, and their launchers.  The causal-matrix kernels are in
+// ccm_inst_multi.hip.
 #include "ccm_device.h"
 #include "ccm_inst.h"
 
@@ -43,38 +44,6 @@ hipError_t launch_crossmap_e(int mode, int grid, const Realization* rzs, const I
   hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), table_lds_bytes(E, table_n_e), st,
                      rzs, items, n_items, next, emb, pts, pj, qord, start, tgt, partial,
                      query_set, window, d, ta);
-  return hipGetLastError();
-}
-
-template <int E>
-hipError_t launch_multi_e(int mode, int grid, const Realization* rzs, const int32_t* self_of,
-                          const Item* items, int n_items, int* next, const float* emb,
-                          const float* pts, const int32_t* pj, const int32_t* qord,
-                          const int32_t* start, const double* tt, int m_series, void* partial,
-                          int query_set, int window, const int32_t* table, int table_n_e,
-                          hipStream_t st) {
-  constexpr int Q = DefaultQ<E>::Q;
-  const TableArgs ta{table, table_lds_words(table_n_e), 0};
-  const size_t dyn = table_lds_bytes(E, table_n_e);
-  using MultiFn = void (*)(const Realization*, const int32_t*, const Item*, int, int*,
-                           const float*, const float*, const int32_t*, const int32_t*,
-                           const int32_t*, const double*, int, Sums*, int, int, TableArgs);
-  MultiFn f;
-  const bool tbl = table_n_e > 0;
-  switch (mode) {
-    case kExclSelf:
-      f = tbl ? k_crossmap_multi<E, Q, kExclSelf, true> : k_crossmap_multi<E, Q, kExclSelf, false>;
-      break;
-    case kKeepSelf:
-      f = tbl ? k_crossmap_multi<E, Q, kKeepSelf, true> : k_crossmap_multi<E, Q, kKeepSelf, false>;
-      break;
-    default:
-      f = tbl ? k_crossmap_multi<E, Q, kWindow, true> : k_crossmap_multi<E, Q, kWindow, false>;
-      break;
-  }
-  hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(kBlock), dyn, st, rzs, self_of, items,
-                     n_items, next, emb, pts, pj, qord, start, tt, m_series,
-                     static_cast<Sums*>(partial), query_set, window, ta);
   return hipGetLastError();
 }
 
@@ -137,11 +106,6 @@ template hipError_t launch_crossmap_e<CCM_INST_E>(int, int, const Realization*, 
                                                   const int32_t*, const int32_t*,
                                                   const int32_t*, const double*, Moments*, int,
                                                   int, Dump, const int32_t*, int, hipStream_t);
-template hipError_t launch_multi_e<CCM_INST_E>(int, int, const Realization*, const int32_t*,
-                                               const Item*, int, int*, const float*,
-                                               const float*, const int32_t*, const int32_t*,
-                                               const int32_t*, const double*, int, void*, int,
-                                               int, const int32_t*, int, hipStream_t);
 template hipError_t launch_nested_e<CCM_INST_E>(int, int, const Realization*, const Item*, int,
                                                 int*, const float*, const float*,
                                                 const int32_t*, const int32_t*, const int32_t*,

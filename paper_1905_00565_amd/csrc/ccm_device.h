@@ -627,10 +627,12 @@ __device__ __forceinline__ void sums_add(Sums& su, double o, double pred, double
   su.v[3] = fma(a, a, su.v[3]);
   su.v[4] = fma(p, p, su.v[4]);
   su.v[5] = fma(a, p, su.v[5]);
-  su.v[6] = fmin(su.v[6], o);
-  su.v[7] = fmax(su.v[7], o);
-  su.v[8] = fmin(su.v[8], pred);
-  su.v[9] = fmax(su.v[9], pred);
+  // series values and predictions are finite: min/max without the
+  // compiler's NaN quieting of the operands
+  su.v[6] = kmin(su.v[6], o);
+  su.v[7] = kmax(su.v[7], o);
+  su.v[8] = kmin(su.v[8], pred);
+  su.v[9] = kmax(su.v[9], pred);
 }
 
 // Order a wavefront's LDS accesses (its lanes read what other lanes wrote).
@@ -641,11 +643,12 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // LDS of the many-target item: per wavefront, one query set's neighbours
-// (w double [K][64], row offsets nj*mp int32 [K][64], qi*mp int32 [64]; the
-// row-offset area first holds the squared distances' bits while the weights
-// are formed); reused afterwards for the wavefronts' per-target sums (Sums
-// [kWaves][64]).  A row offset fits in int32: it is below N*mp <= M*N + N,
-// and the planner caps M*N at INT32_MAX/2.
+// (w double [K][64], byte offsets of the neighbours' rows 8*nj*mp uint32
+// [K][64], of the queries' rows 8*qi*mp uint32 [64]; the row-offset area
+// first holds the squared distances' bits while the weights are formed);
+// reused afterwards for the wavefronts' per-target sums (Sums [kWaves][64]).
+// A byte offset into the table fits in uint32: the planner keeps N*mp*8
+// within 4 GiB.
 template <int E>
 struct MultiLds {
   static constexpr int K = E + 1;
@@ -705,8 +708,14 @@ __device__ __forceinline__ void multi_target_block(const ScanState<E, Q, MODE>& 
   Sums* __restrict__ red = reinterpret_cast<Sums*>(lds);
   const int b = b0 + lane;
   const bool act = b < m_series;
-  const double* __restrict__ Tb = T + (act ? b : 0);
-  const double shift = Tb[0];
+  // lane b's value of a row: the row's byte offset plus 8b from the uniform
+  // table base (one 32-bit add per load)
+  const char* __restrict__ Tc = reinterpret_cast<const char*>(T);
+  const uint32_t lb = act ? (uint32_t)b * 8u : 0u;
+  const auto at = [&](uint32_t row_bytes) {
+    return *reinterpret_cast<const double*>(Tc + (row_bytes + lb));
+  };
+  const double shift = at(0u);
   Sums su;
   sums_init(su);
 #pragma unroll
@@ -718,12 +727,12 @@ __device__ __forceinline__ void multi_target_block(const ScanState<E, Q, MODE>& 
       float nd[K];
       int32_t nj[K];
       select_neighbors<E, Q, MODE>(S, m, nd, nj);
-      sqrow[lane] = S.qi[m] * mp;
+      sqrow[lane] = (int32_t)((uint32_t)(S.qi[m] * mp) * 8u);
 #pragma unroll
       for (int t = 0; t < K; ++t) srow[t * 64 + lane] = __float_as_int(nd[t]);
       stage_weights<K>(srow, sw, lane);
 #pragma unroll
-      for (int t = 0; t < K; ++t) srow[t * 64 + lane] = nj[t] * mp;
+      for (int t = 0; t < K; ++t) srow[t * 64 + lane] = (int32_t)((uint32_t)(nj[t] * mp) * 8u);
     }
     wave_sync();
     if (act) {
@@ -731,10 +740,10 @@ __device__ __forceinline__ void multi_target_block(const ScanState<E, Q, MODE>& 
       // one query per step, its K + 1 loads issued before any is used;
       // pred = w_0 v_0 + ... as a chain of fused multiply-adds
       for (int q = 0; q < nq; ++q) {
+        const double o = at((uint32_t)sqrow[q]);   // first: used first
         double v[K];
 #pragma unroll
-        for (int t = 0; t < K; ++t) v[t] = Tb[srow[t * 64 + q]];
-        const double o = Tb[sqrow[q]];
+        for (int t = 0; t < K; ++t) v[t] = at((uint32_t)srow[t * 64 + q]);
         double pred = sw[q] * v[0];
 #pragma unroll
         for (int t = 1; t < K; ++t) pred = fma(sw[t * 64 + q], v[t], pred);

@@ -701,7 +701,10 @@ Plan make_plan_matrix(const Spec& s) {
   if (s.L.empty()) fail(CCM_E_INVAL, "empty L list");
   if (s.r < 1) fail(CCM_E_INVAL, "r must be >= 1");
   if (s.query_set != 0 && s.query_set != 1) fail(CCM_E_INVAL, "query_set must be 0 or 1");
-  if ((int64_t)s.M * s.N > (int64_t)INT32_MAX / 2) fail(CCM_E_INVAL, "M*N too large");
+  // the kernel addresses the time-major target table (N rows of
+  // target_stride(M) doubles) with 32-bit byte offsets
+  if ((int64_t)target_stride(s.M) * s.N > ((int64_t)1 << 29))
+    fail(CCM_E_INVAL, "M*N too large (the target table must stay within 4 GiB)");
   const int32_t E = s.E[0], tau = s.tau[0];
   if (E < 1 || E > kMaxE) fail(CCM_E_INVAL, "E must be in [1, 10]");
   if (tau < 1) fail(CCM_E_INVAL, "tau must be >= 1");

@@ -69,6 +69,34 @@ def test_matrix_small_vs_oracle(ctx, orc):
     close(got, want)
 
 
+def test_matrix_zero_distances(ctx, orc):
+    """Series quantised to a few levels: many queries have a first neighbour
+    at distance zero (the zero-distance weight rule) beside queries that do
+    not, inside one wavefront, so the per-target stage forms its weights on
+    both sides of that branch at once.  Against the oracle and against the
+    pairwise form."""
+    S = np.round(small_network(4, 700) * 40.0) / 40.0
+    M = S.shape[0]
+    L = [60, 698]
+    r = 2
+    rho = ctx.ccm_matrix(S, 2, 1, L, r, 13)
+    tasks, where = [], []
+    for a in range(M):
+        for b in range(M):
+            if a == b:
+                continue
+            for il, l in enumerate(L):
+                for ri in range(r):
+                    tasks.append((S[a], S[b], 2, 1, l, ri, 13, 0, 0))
+                    where.append((a, b, il, ri))
+    want = orc.realizations_threaded(tasks)
+    got = [rho[w] for w in where]
+    close(got, want)
+    for a, b in [(0, 1), (2, 3)]:
+        rxy, _, _ = ctx.ccm(S[b], S[a], 2, 1, L, r, 13)
+        assert np.max(np.abs(rho[a, b] - rxy)) < 1e-12
+
+
 def test_matrix_equals_pairwise_ccm(ctx):
     S = small_network()
     L = [30, 200]

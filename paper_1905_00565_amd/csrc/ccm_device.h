@@ -445,8 +445,68 @@ __device__ __forceinline__ void scan_range(const float* __restrict__ pts,
       b -= G;
     }
   }
-  for (; f + G <= L; f += G) scan_group<E, Q, MODE, G>(pts, pj, f, S.qc, S.qi, window, S.key);
-  for (; b - G >= 0; b -= G) scan_group<E, Q, MODE, G>(pts, pj, b - G, S.qc, S.qi, window, S.key);
+  // The one-sided remainder (the longer side), pipelined the same way over
+  // consecutive groups of that side; a last request with no group after it
+  // re-reads the current group (in bounds, never used).
+  if constexpr (kPipeRest[E] != 0) {
+    const int nf = (L - f) / G;
+    if (nf > 0) {
+      Chunk<E, G> A, B;
+      load_chunk<E, G>(A, pts, pj, f);
+      int k = 0;
+      for (; k + 1 < nf; k += 2) {
+        settle_chunk<E, G>(A);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk<E, G>(B, pts, pj, f + G);
+        __builtin_amdgcn_sched_barrier(0);
+        check_chunk<E, Q, MODE, G>(A, S.qc, S.qi, window, S.key);
+        f += G;
+        settle_chunk<E, G>(B);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk<E, G>(A, pts, pj, k + 2 < nf ? f + G : f);
+        __builtin_amdgcn_sched_barrier(0);
+        check_chunk<E, Q, MODE, G>(B, S.qc, S.qi, window, S.key);
+        f += G;
+      }
+      if (k < nf) {
+        settle_chunk<E, G>(A);
+        __builtin_amdgcn_sched_barrier(0);
+        check_chunk<E, Q, MODE, G>(A, S.qc, S.qi, window, S.key);
+        f += G;
+      }
+    }
+    const int nb = b / G;
+    if (nb > 0) {
+      Chunk<E, G> A, B;
+      load_chunk<E, G>(A, pts, pj, b - G);
+      int k = 0;
+      for (; k + 1 < nb; k += 2) {
+        settle_chunk<E, G>(A);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk<E, G>(B, pts, pj, b - 2 * G);
+        __builtin_amdgcn_sched_barrier(0);
+        check_chunk<E, Q, MODE, G>(A, S.qc, S.qi, window, S.key);
+        b -= G;
+        settle_chunk<E, G>(B);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk<E, G>(A, pts, pj, k + 2 < nb ? b - 2 * G : b - G);
+        __builtin_amdgcn_sched_barrier(0);
+        check_chunk<E, Q, MODE, G>(B, S.qc, S.qi, window, S.key);
+        b -= G;
+      }
+      if (k < nb) {
+        settle_chunk<E, G>(A);
+        __builtin_amdgcn_sched_barrier(0);
+        check_chunk<E, Q, MODE, G>(A, S.qc, S.qi, window, S.key);
+        b -= G;
+      }
+    }
+  } else {
+    for (; f + G <= L; f += G)
+      scan_group<E, Q, MODE, G>(pts, pj, f, S.qc, S.qi, window, S.key);
+    for (; b - G >= 0; b -= G)
+      scan_group<E, Q, MODE, G>(pts, pj, b - G, S.qc, S.qi, window, S.key);
+  }
   for (; f < L; ++f) scan_group<E, Q, MODE, 1>(pts, pj, f, S.qc, S.qi, window, S.key);
   for (; b > 0; --b) scan_group<E, Q, MODE, 1>(pts, pj, b - 1, S.qc, S.qi, window, S.key);
 }

@@ -51,6 +51,14 @@
 #define CCM_BOUND_CHECK {0, 1, 0, 1, 0, 0, 0, 0, 0, 0, 0}
 #endif
 
+// One-sided remainder of the outward scan (index E): 1 = software-pipelined
+// like the two-sided part (its scalar loads issued a group ahead), 0 = each
+// group loaded when it is checked (at E >= 6 the pipelined form's extra
+// scalar registers cost more than the loads it hides).
+#ifndef CCM_PIPE_REST
+#define CCM_PIPE_REST {0, 1, 1, 1, 1, 1, 0, 0, 0, 0, 0}
+#endif
+
 // Causal matrix: minimum wavefronts per SIMD of the many-target kernel (its
 // per-target stage holds more state than the plain scan's moments; 0: free).
 #ifndef CCM_MULTI_W
@@ -59,6 +67,7 @@
 
 namespace ccmk {
 constexpr int kBoundCheck[11] = CCM_BOUND_CHECK;
+constexpr int kPipeRest[11] = CCM_PIPE_REST;
 constexpr int kMultiW[11] = CCM_MULTI_W;
 constexpr int kNestedW[11] = CCM_NESTED_W;
 constexpr int kTuneQ[11] = CCM_TUNE_Q;

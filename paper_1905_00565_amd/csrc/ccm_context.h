@@ -80,6 +80,10 @@ struct ccm_ctx {
   std::vector<ccmh::EvPair> ev_pending, ev_free;
   ccm_profile prof{};
   std::unique_ptr<ccmh::Exec> exec;   // the most recent plan
+  // pinned staging of the host-array forms' series and results (one
+  // buffer, grown as needed; calls on a context are serialised)
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
 };
 
 namespace ccmh {

@@ -12,6 +12,9 @@
 #include "ccm_host.h"
 #include "ccm_context.h"
 
+#include <cstring>
+#include <initializer_list>
+
 using namespace ccmh;
 
 namespace {
@@ -372,6 +375,7 @@ void ccm_destroy(ccm_ctx* c) {
       (void)hipEventDestroy(e.b);
     }
     if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->pinned) (void)hipHostFree(c->pinned);
   }
   delete c;
 }
@@ -389,6 +393,35 @@ ccm_status ccm_set_wave_limit(ccm_ctx* c, uint64_t bytes) {
   });
 }
 
+namespace {
+
+// The context's pinned staging buffer, at least `bytes` long.  Host arrays
+// are copied through it so that the transfers are asynchronous DMA of
+// pinned memory rather than staged pageable copies.
+double* pinned_stage(ccm_ctx* c, size_t bytes) {
+  if (c->pinned_bytes < bytes) {
+    if (c->pinned) HIPCHK(hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+    HIPCHK(hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault));
+    c->pinned_bytes = bytes;
+  }
+  return static_cast<double*>(c->pinned);
+}
+
+// Series in: n doubles from each of the host arrays, to dst on the device.
+void upload_series(ccm_ctx* c, double* dst, std::initializer_list<const double*> src,
+                   int64_t n, double* stage) {
+  int64_t o = 0;
+  for (const double* a : src) {
+    std::memcpy(stage + o, a, (size_t)n * 8);
+    o += n;
+  }
+  HIPCHK(hipMemcpyAsync(dst, stage, (size_t)o * 8, hipMemcpyHostToDevice, c->stream));
+}
+
+}  // namespace
+
 ccm_status ccm_sweep(ccm_ctx* c, const double* X, const double* Y, int64_t N,
                      const int32_t* E, int32_t nE, const int32_t* tau, int32_t ntau,
                      const int64_t* L, int32_t nL, int32_t r, uint64_t seed,
@@ -400,11 +433,13 @@ ccm_status ccm_sweep(ccm_ctx* c, const double* X, const double* Y, int64_t N,
     check_host_series(X, N, "X");
     check_host_series(Y, N, "Y");
     Exec* ex = prepare(c, s);
-    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>() + N, Y, N * 8, hipMemcpyHostToDevice, c->stream));
+    const int64_t n_out = ex->plan.n_out;
+    double* h = pinned_stage(c, (size_t)std::max<int64_t>(2 * N, n_out) * 8);
+    upload_series(c, ex->d_s64.as<double>(), {X, Y}, N, h);
     run(c, ex, c->stream);
-    HIPCHK(hipMemcpyAsync(rho, ex->d_out.p, ex->plan.n_out * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(h, ex->d_out.p, n_out * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    std::memcpy(rho, h, (size_t)n_out * 8);
   });
 }
 
@@ -418,14 +453,14 @@ ccm_status ccm(ccm_ctx* c, const double* X, const double* Y, int64_t N, int32_t 
     check_host_series(X, N, "X");
     check_host_series(Y, N, "Y");
     Exec* ex = prepare(c, s);
-    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>() + N, Y, N * 8, hipMemcpyHostToDevice, c->stream));
-    run(c, ex, c->stream);
     const int64_t half = (int64_t)nL * r;
-    HIPCHK(hipMemcpyAsync(rho_xy, ex->d_out.p, half * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(rho_yx, ex->d_out.as<double>() + half, half * 8,
-                          hipMemcpyDeviceToHost, c->stream));
+    double* h = pinned_stage(c, (size_t)std::max<int64_t>(2 * N, 2 * half) * 8);
+    upload_series(c, ex->d_s64.as<double>(), {X, Y}, N, h);
+    run(c, ex, c->stream);
+    HIPCHK(hipMemcpyAsync(h, ex->d_out.p, 2 * half * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    std::memcpy(rho_xy, h, (size_t)half * 8);
+    std::memcpy(rho_yx, h + half, (size_t)half * 8);
     if (L_eff)
       for (int i = 0; i < nL; ++i) L_eff[i] = ex->plan.L_eff[i];
   });
@@ -479,10 +514,13 @@ ccm_status ccm_matrix(ccm_ctx* c, const double* S, int32_t M, int64_t N, int32_t
     s.wave_limit = c->wave_limit;
     check_host_series(S, (int64_t)M * N, "S");
     Exec* ex = prepare(c, s);
-    HIPCHK(hipMemcpyAsync(ex->d_s64.p, S, (size_t)M * N * 8, hipMemcpyHostToDevice, c->stream));
+    const int64_t n_out = ex->plan.n_out;
+    double* h = pinned_stage(c, (size_t)std::max<int64_t>((int64_t)M * N, n_out) * 8);
+    upload_series(c, ex->d_s64.as<double>(), {S}, (int64_t)M * N, h);
     run(c, ex, c->stream);
-    HIPCHK(hipMemcpyAsync(rho, ex->d_out.p, ex->plan.n_out * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(h, ex->d_out.p, n_out * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    std::memcpy(rho, h, (size_t)n_out * 8);
   });
 }
 

@@ -197,7 +197,9 @@ ccm_status ccm_sweep(ccm_ctx *ctx, const double *X, const double *Y,
  *   rho         host double[M][M][nL][r]: rho[a][b] is the skill of
  *               predicting series b from the manifold of series a (high when
  *               b drives a); the diagonal is NaN
- * Requires M >= 2; other rules as for ccm().
+ * Requires M >= 2 and (M rounded up to even) * N <= 2^29 (the targets are
+ * kept as one time-major FP64 table within 4 GiB), else CCM_E_INVAL; other
+ * rules as for ccm().
  */
 ccm_status ccm_matrix(ccm_ctx *ctx, const double *S, int32_t M, int64_t N,
                       int32_t E, int32_t tau, const int64_t *L, int32_t nL,

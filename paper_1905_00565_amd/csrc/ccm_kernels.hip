@@ -733,6 +733,40 @@ hipError_t launch_table_build(int E, const TableJob* jobs, int n_jobs, int max_n
   }
 }
 
+// Two device arrays of n doubles to one buffer, or one buffer to two
+// arrays, in a single launch (the device forms' series in and results out).
+__global__ void k_copy_pair(const double* __restrict__ a, const double* __restrict__ b,
+                            int64_t n, double* __restrict__ dst) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < 2 * n;
+       x += (int64_t)gridDim.x * blockDim.x)
+    dst[x] = x < n ? a[x] : b[x - n];
+}
+
+__global__ void k_split_pair(const double* __restrict__ src, int64_t n, double* __restrict__ a,
+                             double* __restrict__ b) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < 2 * n;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    if (x < n)
+      a[x] = src[x];
+    else
+      b[x - n] = src[x];
+  }
+}
+
+hipError_t launch_copy_pair(const double* a, const double* b, int64_t n, double* dst,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_copy_pair<<<blocks_for(2 * n, 256), 256, 0, st>>>(a, b, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_pair(const double* src, int64_t n, double* a, double* b,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_split_pair<<<blocks_for(2 * n, 256), 256, 0, st>>>(src, n, a, b);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample_nested(const NestedJob* jobs, int64_t n_jobs, int32_t* scratch,
                                 int32_t* out_pool, hipStream_t st) {
   if (n_jobs <= 0) return hipSuccess;

@@ -476,8 +476,7 @@ ccm_status ccm_sweep_dev(ccm_ctx* c, const double* X, const double* Y, int64_t N
     s.wave_limit = c->wave_limit;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Exec* ex = prepare(c, s);
-    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>() + N, Y, N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_copy_pair(X, Y, N, ex->d_s64.as<double>(), st));
     run(c, ex, st);
     HIPCHK(hipMemcpyAsync(rho, ex->d_out.p, ex->plan.n_out * 8, hipMemcpyDeviceToDevice, st));
   });
@@ -493,13 +492,10 @@ ccm_status ccm_dev(ccm_ctx* c, const double* X, const double* Y, int64_t N, int3
     s.wave_limit = c->wave_limit;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Exec* ex = prepare(c, s);
-    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>(), X, N * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(ex->d_s64.as<double>() + N, Y, N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_copy_pair(X, Y, N, ex->d_s64.as<double>(), st));
     run(c, ex, st);
     const int64_t half = (int64_t)nL * r;
-    HIPCHK(hipMemcpyAsync(rho_xy, ex->d_out.p, half * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(rho_yx, ex->d_out.as<double>() + half, half * 8,
-                          hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_split_pair(ex->d_out.as<double>(), half, rho_xy, rho_yx, st));
     if (L_eff)
       for (int i = 0; i < nL; ++i) L_eff[i] = ex->plan.L_eff[i];
   });

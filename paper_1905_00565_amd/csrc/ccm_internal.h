@@ -175,11 +175,6 @@ struct Dump {
 // Queries per lane of the cross-map kernel of E (a tile holds kBlock times
 // as many); the same for batched launches and the per-query hook.
 int crossmap_queries_per_lane(int E);
-// dst[0, n) = a, dst[n, 2n) = b; and the reverse split (device arrays).
-hipError_t launch_copy_pair(const double* a, const double* b, int64_t n, double* dst,
-                            hipStream_t st);
-hipError_t launch_split_pair(const double* src, int64_t n, double* a, double* b,
-                             hipStream_t st);
 // E-sweep sharing: queries per lane of the scan at E_max (its key registers
 // grow as E_max^2, so this falls with E_max).
 int shared_queries_per_lane(int emax);

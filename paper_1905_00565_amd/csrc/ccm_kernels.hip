@@ -38,6 +38,7 @@
 // still evaluated.
 #include "ccm_device.h"
 #include "ccm_inst.h"
+#include "ccm_copy.h"
 
 namespace ccmk {
 

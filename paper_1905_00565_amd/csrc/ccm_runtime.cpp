@@ -11,6 +11,7 @@
 // caller memory.
 #include "ccm_host.h"
 #include "ccm_context.h"
+#include "ccm_copy.h"
 
 #include <cstring>
 #include <initializer_list>

@@ -128,6 +128,25 @@ def test_neighbors_tile_boundaries(ctx, orc):
                 rho_close(g[3], o[3])
 
 
+def test_neighbors_every_small_library(ctx, orc):
+    """Every library size from E + 2 to E + 73 for E = 1..5 (the outward
+    scan's one-sided remainder is software-pipelined there): odd and even
+    numbers of remaining groups on either side, scan starts at both ends and
+    inside, and the single-position tails.  Bit-exact neighbours."""
+    rng = np.random.default_rng(23)
+    for E in range(1, 6):
+        N = 180 + E
+        ne = N - (E - 1)
+        S = rng.random(N)
+        T = rng.random(N)
+        for L in range(E + 2, E + 74):
+            lib = np.sort(rng.choice(ne, size=L, replace=False)).astype(np.int32)
+            g = ctx.ccm_neighbors(S, T, E, 1, lib)
+            o = orc.neighbors(S, T, E, 1, lib)
+            assert np.array_equal(g[0], o[0]) and np.array_equal(g[1], o[1]), (E, L)
+            assert np.max(np.abs(g[2] - o[2])) < TOL
+
+
 def test_small_workload_full(ctx, orc):
     """Coupled logistic N=1000, E=2, tau=1, L=100..1000, r=100: every rho."""
     w = synth.workload_small()
